@@ -1,0 +1,206 @@
+/*
+ * argus.h - C ABI of libargus: PSF-matched difference imaging on MI355X.
+ *
+ * The calls follow the per-frame reduction that arXiv:2207.14304 describes
+ * for the Argus Array:
+ *   - calibration masters (darks, flats, bad-pixel masks, noise maps) and
+ *     reference frames live on the GPU for a whole pointing (Compute Nodes
+ *     section; first paragraph of Pipeline Implementation);
+ *   - every full frame is calibrated: dark subtraction, flat fielding, bad
+ *     pixel masking (Image Management section);
+ *   - references are coadds of many registered frames (Deep Coaddition in
+ *     Sky Segments; Transient Alerts);
+ *   - transients come from direct, PSF-matched image subtraction against the
+ *     reference (Transient Alerts; Table 2, "direct image subtraction").
+ * The paper does not print the subtraction algorithm; the kernel model here
+ * is the Gaussian-basis kernel with polynomial spatial variation of Alard &
+ * Lupton (1998) and Alard (2000), fit by weighted linear least squares.
+ *
+ * Conventions shared by every call
+ *   - Images are row-major [y][x]; argus_dims.pitch is the row stride in
+ *     ELEMENTS (>= width) and applies to every image argument of a call.
+ *   - Unless marked "host", every pointer is a device pointer on the ctx's
+ *     device.  The caller allocates and owns all inputs and outputs; the
+ *     library never frees caller memory.  The library owns only its ctx
+ *     workspace, grown on first need (never during stream capture).
+ *   - Each call validates its arguments on the host and returns ARGUS_OK or a
+ *     negative ARGUS_E* code synchronously; argus_last_error() then describes
+ *     the failure.  On success the work is enqueued on the ctx stream and the
+ *     call returns WITHOUT synchronising.  Data-dependent failures (a
+ *     singular fit, candidate overflow) are reported in device outputs.
+ *   - Convolution is true convolution: (R (x) K)(x, y) = sum_{u,v} K(u,v)
+ *     R(x-u, y-v) with kernel stamps stored K[v+h][u+h].
+ *   - Normalised coordinates xt = (2x-(W-1))/(W-1), yt = (2y-(H-1))/(H-1);
+ *     spatial monomials P_m = xt^p yt^q ordered p = 0..D outer, q = 0..D-p.
+ */
+#ifndef ARGUS_H
+#define ARGUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define ARGUS_OK        0
+#define ARGUS_EINVAL   (-1)   /* null pointer, bad scalar argument          */
+#define ARGUS_ESHAPE   (-2)   /* inconsistent sizes / pitch / spec          */
+#define ARGUS_ENOMEM   (-3)   /* workspace allocation failed                */
+#define ARGUS_EHIP     (-4)   /* a HIP runtime call failed                  */
+#define ARGUS_EBUSY    (-5)   /* would allocate while the stream captures   */
+/* per-solve status written by argus_fit_kernel (device int32 array)        */
+#define ARGUS_ESINGULAR (-20) /* non-positive diagonal or pivot             */
+#define ARGUS_ETOOFEW   (-21) /* fewer fit pixels than unknowns             */
+
+/* ---- mask bits (uint8 masks) ------------------------------------------- */
+#define ARGUS_BAD    0x01u  /* bad pixel (bpm, flat <= 0, non-finite master) */
+#define ARGUS_SAT    0x02u  /* raw >= saturation                             */
+#define ARGUS_EDGE   0x04u  /* within the kernel half-width of the border    */
+#define ARGUS_NODATA 0x08u  /* no usable frame in the coadd                  */
+#define ARGUS_FOOT   0x10u  /* a flagged reference pixel in the footprint    */
+#define ARGUS_DET    0x20u  /* SNR >= threshold                              */
+#define ARGUS_CAND   0x40u  /* DET and raster-ordered 8-neighbour maximum    */
+
+/* ---- fit modes and precisions ------------------------------------------ */
+#define ARGUS_FIT_GLOBAL   0  /* one solve; tiles only order the partial sums */
+#define ARGUS_FIT_PER_TILE 1  /* one independent solve per tile              */
+#define ARGUS_FP32   0        /* normal equations on FP32 MFMA               */
+#define ARGUS_BF16X3 1        /* hi/lo-split BF16 MFMA, FP32 accumulation    */
+
+typedef struct argus_ctx argus_ctx;
+
+typedef struct {
+    int32_t width;
+    int32_t height;
+    int64_t pitch;            /* row stride in elements, >= width */
+} argus_dims;
+
+/* Kernel model: n_gauss Gaussians of width sigma[g] times monomials u^i v^j
+ * with i + j <= degree[g] (g outer, then i, then j), sampled on the integer
+ * grid of half-width half_width, normalised so that basis 0 has unit sum and
+ * every other basis has zero sum and unit L2 norm.  spatial_degree D is the
+ * degree of the polynomial in (xt, yt) multiplying every basis; bg_degree is
+ * that of the additive background (<= D).  Unknowns:
+ *   n = nb * (D+1)(D+2)/2 + (Dbg+1)(Dbg+2)/2,  nb = number of bases (<= 31).
+ * Tiles partition the frame at floor(i*W/tiles_x) (and likewise in y). */
+typedef struct {
+    int32_t n_gauss;          /* 1..4 */
+    double  sigma[4];
+    int32_t degree[4];
+    int32_t half_width;       /* h, 1..15: stamps are (2h+1)^2 */
+    int32_t spatial_degree;   /* 0..2 */
+    int32_t bg_degree;        /* 0..spatial_degree */
+    int32_t tiles_x, tiles_y; /* >= 1 */
+    int32_t mode;             /* ARGUS_FIT_GLOBAL or ARGUS_FIT_PER_TILE */
+    int32_t precision;        /* ARGUS_FP32 or ARGUS_BF16X3 */
+} argus_kernel_spec;
+
+typedef struct {
+    int32_t x, y;
+    float snr, flux, flux_err;
+} argus_candidate;
+
+/* ---- context ------------------------------------------------------------ */
+/* Create a context on HIP device `device`; work goes to the null stream until
+ * argus_ctx_set_stream.  One context per host thread. */
+int  argus_ctx_create(int device, argus_ctx **out);
+void argus_ctx_destroy(argus_ctx *ctx);
+/* hip_stream is a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
+int  argus_ctx_set_stream(argus_ctx *ctx, void *hip_stream);
+/* Message of the most recent synchronous failure on this ctx ("" if none). */
+const char *argus_last_error(const argus_ctx *ctx);
+/* Device time in milliseconds of the most recent launch of the named
+ * internal kernel, or -1 if timing is off; timing records HIP events around
+ * each launch when enabled (for measurement only). */
+int  argus_ctx_set_timing(argus_ctx *ctx, int enable);
+float argus_kernel_time_ms(argus_ctx *ctx, const char *kernel);
+
+/* ---- calibration (Image Management section) ----------------------------
+ * Per pixel:  cal  = (raw - dark) / flat
+ *             var  = (max(raw - dark, 0)/gain + read_noise^2/gain^2) / flat^2
+ *             mask = BAD if bpm != 0, flat <= 0 or flat/dark not finite;
+ *                    SAT if raw >= sat_adu.   BAD pixels get cal = var = 0.
+ * raw u16, dark/flat f32 (dark includes bias), bpm u8 (nullable = none);
+ * outputs cal f32, var f32 (nullable), mask u8.  gain in e-/ADU (> 0),
+ * read_noise in e- (Table 1 quotes 1.7 e-).  Streaming; HBM-bound. */
+int argus_calibrate(argus_ctx *ctx, argus_dims dims,
+                    const uint16_t *raw, const float *dark, const float *flat,
+                    const uint8_t *bpm, float gain, float read_noise,
+                    uint16_t sat_adu, float *cal, float *var, uint8_t *mask);
+
+/* ---- reference coadd (Deep Coaddition; Transient Alerts) ----------------
+ * n_frames (1..8) registered calibrated frames -> clipped mean per pixel.
+ * Start with the frames whose mask has neither BAD nor SAT; up to max_iter
+ * times: stop if <= 2 remain; c = median of values, s2 = median of variances
+ * (even count: mean of the middle two); reject |x - c| > kappa*sqrt(s2);
+ * stop if nothing is rejected or fewer than 2 would remain.  ref = mean,
+ * ref_var = sum(var)/m^2, n_used = m (nullable); ref_mask NODATA if no frame
+ * was usable (ref = ref_var = 0), SAT if any frame is SAT there.
+ * cal/var/mask are HOST arrays of n_frames DEVICE pointers.  Decisions are
+ * taken in FP64.  Streaming; HBM-bound. */
+int argus_coadd(argus_ctx *ctx, argus_dims dims, int n_frames,
+                const float *const *cal, const float *const *var,
+                const uint8_t *const *mask, float kappa, int max_iter,
+                float *ref, float *ref_var, uint8_t *ref_mask, uint8_t *n_used);
+
+/* Number of unknowns per solve and number of solves for a spec. */
+int argus_kernel_dims(const argus_kernel_spec *spec, int *n_unknowns, int *n_solves);
+
+/* ---- kernel fit (direct subtraction of Transient Alerts / Table 2) ------
+ * Fit set: pixels with h <= x <= W-1-h and h <= y <= H-1-h, sci_mask == 0,
+ * ref_mask == 0 over the (2h+1)^2 footprint and sci_var + ref_var > 0;
+ * weights w = 1/(sci_var + ref_var).  Design row of pixel p: P_m(p) *
+ * (ref (x) B_k)(p) at index k*nP + m, then the background block P_m(p).
+ * Normal equations are accumulated per tile (FP32 products, FP64 sums),
+ * added in FP64 (all tiles for GLOBAL), Jacobi-scaled and Cholesky-solved in
+ * FP64 on the GPU.  Outputs (device): coeffs f64 [n_solves][n] (NaN where the
+ * solve failed), n_fit i64 [n_solves] (nullable), status i32 [n_solves]
+ * (ARGUS_OK, ARGUS_ESINGULAR or ARGUS_ETOOFEW). */
+int argus_fit_kernel(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
+                     const float *ref, const float *ref_var, const uint8_t *ref_mask,
+                     const float *sci, const float *sci_var, const uint8_t *sci_mask,
+                     double *coeffs, int64_t *n_fit, int32_t *status);
+
+/* K_m = sum_k a_{k nP + m} B_k and bg_m = a_{nb nP + m}, evaluated in FP64.
+ * stamps f32 [n_solves][nP][2h+1][2h+1], bg f32 [n_solves][nPbg]. */
+int argus_expand_kernel(argus_ctx *ctx, const argus_kernel_spec *spec,
+                        const double *coeffs, float *stamps, float *bg);
+
+/* ---- PSF-matched convolution and subtraction ------------------------------
+ * Per pixel p, with K_p = sum_m P_m(p) K_m of the solve owning p:
+ *   D = S - (sum_{u,v} K_p(u,v) R(x-u, y-v) + sum_m bg_m P_m(p))
+ *   V = var_S + sum_{u,v} K_p(u,v)^2 var_R(x-u, y-v)
+ * diff_mask = sci_mask | EDGE (within h of the border) | FOOT (any ref_mask
+ * bit in the footprint); D = V = 0 where diff_mask != 0.
+ * chi2 f64 [n_solves] (nullable): sum over the fit set of D^2/(var_S+var_R);
+ * n_chi2 i64 [n_solves] (nullable): size of that set.  Stamps and bg as
+ * written by argus_expand_kernel (any caller kernel works, e.g. a delta). */
+int argus_subtract(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
+                   const float *stamps, const float *bg,
+                   const float *ref, const float *ref_var, const uint8_t *ref_mask,
+                   const float *sci, const float *sci_var, const uint8_t *sci_mask,
+                   float *diff, float *diff_var, uint8_t *diff_mask,
+                   double *chi2, int64_t *n_chi2);
+
+/* ---- detection (Transient Alerts: candidates from the subtraction) --------
+ * snr = D/sqrt(V) where diff_mask == 0 and V > 0, else 0 (f32, nullable);
+ * det_mask = DET where snr >= threshold, | CAND where additionally snr is
+ * strictly above every 8-neighbour earlier in raster order and >= every
+ * later one (off-image neighbours count as -inf).  Per candidate, with the
+ * caller's unit-sum PSF psf [2r+1][2r+1] (r = psf_half, 0..15) over unmasked
+ * in-image pixels: Q = sum P^2/V, flux = (sum P D/V)/Q, flux_err = Q^-1/2
+ * (FP64 sums).  cands (device, capacity entries) holds the first `capacity`
+ * candidates in raster order; *n_cands (device i32) receives the TRUE count,
+ * so *n_cands > capacity signals truncation. */
+int argus_detect(argus_ctx *ctx, argus_dims dims,
+                 const float *diff, const float *diff_var, const uint8_t *diff_mask,
+                 float threshold, const float *psf, int psf_half,
+                 float *snr, uint8_t *det_mask,
+                 argus_candidate *cands, int32_t capacity, int32_t *n_cands);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARGUS_H */

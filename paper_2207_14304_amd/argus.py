@@ -1,0 +1,228 @@
+"""Python binding of libargus (ctypes).
+
+Argument marshalling only: every step runs in the HIP library.  Tensors are
+torch device tensors used for their memory and stream; the calls enqueue on
+``torch.cuda.current_stream()`` and do not synchronise.  There is no CPU
+fallback: loading fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libargus.so")
+
+OK, EINVAL, ESHAPE, ENOMEM, EHIP, EBUSY = 0, -1, -2, -3, -4, -5
+ESINGULAR, ETOOFEW = -20, -21
+BAD, SAT, EDGE, NODATA, FOOT, DET, CAND = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20, 0x40
+FIT_GLOBAL, FIT_PER_TILE = 0, 1
+FP32, BF16X3 = 0, 1
+
+# every symbol declared in include/argus.h
+SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "argus_last_error",
+           "argus_ctx_set_timing", "argus_kernel_time_ms", "argus_calibrate", "argus_coadd",
+           "argus_kernel_dims", "argus_fit_kernel", "argus_expand_kernel", "argus_subtract",
+           "argus_detect")
+
+
+class Dims(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("pitch", C.c_int64)]
+
+
+class KernelSpec(C.Structure):
+    _fields_ = [("n_gauss", C.c_int32), ("sigma", C.c_double * 4), ("degree", C.c_int32 * 4),
+                ("half_width", C.c_int32), ("spatial_degree", C.c_int32),
+                ("bg_degree", C.c_int32), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("mode", C.c_int32), ("precision", C.c_int32)]
+
+
+CANDIDATE_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("snr", np.float32),
+                            ("flux", np.float32), ("flux_err", np.float32)])
+
+
+def make_spec(sigmas=(0.7, 1.5, 3.0), degrees=(4, 3, 2), half_width=7, spatial_degree=0,
+              bg_degree=0, tiles_x=1, tiles_y=1, mode=FIT_GLOBAL, precision=FP32) -> KernelSpec:
+    s = KernelSpec()
+    s.n_gauss = len(sigmas)
+    for i, (sg, d) in enumerate(zip(sigmas, degrees)):
+        s.sigma[i] = float(sg)
+        s.degree[i] = int(d)
+    s.half_width = half_width
+    s.spatial_degree = spatial_degree
+    s.bg_degree = bg_degree
+    s.tiles_x, s.tiles_y = tiles_x, tiles_y
+    s.mode, s.precision = mode, precision
+    return s
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libargus.so and declare the signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libargus.so not built at {path}; run python -m paper_2207_14304_amd.build")
+    lib = C.CDLL(path)
+    vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    lib.argus_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.argus_ctx_destroy.argtypes = [vp]
+    lib.argus_ctx_destroy.restype = None
+    lib.argus_ctx_set_stream.argtypes = [vp, vp]
+    lib.argus_last_error.argtypes = [vp]
+    lib.argus_last_error.restype = C.c_char_p
+    lib.argus_ctx_set_timing.argtypes = [vp, C.c_int]
+    lib.argus_kernel_time_ms.argtypes = [vp, C.c_char_p]
+    lib.argus_kernel_time_ms.restype = f32
+    lib.argus_calibrate.argtypes = [vp, Dims, vp, vp, vp, vp, f32, f32, C.c_uint16, vp, vp, vp]
+    lib.argus_coadd.argtypes = [vp, Dims, C.c_int, vp, vp, vp, f32, C.c_int, vp, vp, vp, vp]
+    lib.argus_kernel_dims.argtypes = [C.POINTER(KernelSpec), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 9
+    lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
+    lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 13
+    lib.argus_detect.argtypes = [vp, Dims, vp, vp, vp, f32, vp, C.c_int, vp, vp, vp, i32, vp]
+    for name in SYMBOLS:
+        if name not in ("argus_ctx_destroy", "argus_last_error", "argus_kernel_time_ms"):
+            getattr(lib, name).restype = C.c_int
+    _ = (i64,)
+    _lib = lib
+    return lib
+
+
+class ArgusError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"argus error {code}: {msg}")
+        self.code = code
+
+
+def kernel_dims(spec: KernelSpec):
+    lib = load()
+    n, s = C.c_int(), C.c_int()
+    rc = lib.argus_kernel_dims(C.byref(spec), C.byref(n), C.byref(s))
+    if rc:
+        raise ArgusError(rc, "bad kernel spec")
+    return n.value, s.value
+
+
+def _ptr(t, dtype=None):
+    """Device address of a torch tensor (or 0 for None), checking dtype."""
+    if t is None:
+        return None
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    return t.data_ptr()
+
+
+def _dims(t):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("images are 2-D, row-major with unit column stride")
+    return Dims(t.shape[1], t.shape[0], t.stride(0))
+
+
+class Context:
+    """An argus_ctx bound to the current torch stream of ``device``."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.argus_ctx_create(device, C.byref(h))
+        if rc:
+            raise ArgusError(rc, "argus_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.argus_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind(self):
+        s = self._torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.argus_ctx_set_stream(self.h, C.c_void_p(s))
+
+    def _check(self, rc):
+        if rc:
+            raise ArgusError(rc, self.lib.argus_last_error(self.h).decode())
+
+    def set_timing(self, on: bool):
+        self._check(self.lib.argus_ctx_set_timing(self.h, int(on)))
+
+    def kernel_time_ms(self, name: str) -> float:
+        return float(self.lib.argus_kernel_time_ms(self.h, name.encode()))
+
+    # ---- calls ------------------------------------------------------------
+    def calibrate(self, raw, dark, flat, bpm, gain, read_noise, sat_adu, cal, var, mask):
+        torch = self._torch
+        self._bind()
+        self._check(self.lib.argus_calibrate(
+            self.h, _dims(raw), _ptr(raw, torch.uint16), _ptr(dark, torch.float32),
+            _ptr(flat, torch.float32), _ptr(bpm, torch.uint8), float(gain), float(read_noise),
+            int(sat_adu), _ptr(cal, torch.float32), _ptr(var, torch.float32),
+            _ptr(mask, torch.uint8)))
+
+    def coadd(self, cals, vars_, masks, kappa, max_iter, ref, ref_var, ref_mask, n_used=None):
+        torch = self._torch
+        self._bind()
+        n = len(cals)
+        P = C.c_void_p * n
+        pc = P(*[_ptr(c, torch.float32) for c in cals])
+        pv = P(*[_ptr(v, torch.float32) for v in vars_])
+        pm = P(*[_ptr(m, torch.uint8) for m in masks])
+        self._check(self.lib.argus_coadd(
+            self.h, _dims(cals[0]), n, pc, pv, pm, float(kappa), int(max_iter),
+            _ptr(ref, torch.float32), _ptr(ref_var, torch.float32), _ptr(ref_mask, torch.uint8),
+            _ptr(n_used, torch.uint8)))
+
+    def fit_kernel(self, spec, ref, ref_var, ref_mask, sci, sci_var, sci_mask, coeffs, n_fit,
+                   status):
+        torch = self._torch
+        self._bind()
+        self._check(self.lib.argus_fit_kernel(
+            self.h, _dims(ref), C.byref(spec), _ptr(ref, torch.float32),
+            _ptr(ref_var, torch.float32), _ptr(ref_mask, torch.uint8), _ptr(sci, torch.float32),
+            _ptr(sci_var, torch.float32), _ptr(sci_mask, torch.uint8),
+            _ptr(coeffs, torch.float64), _ptr(n_fit, torch.int64), _ptr(status, torch.int32)))
+
+    def expand_kernel(self, spec, coeffs, stamps, bg):
+        torch = self._torch
+        self._bind()
+        self._check(self.lib.argus_expand_kernel(
+            self.h, C.byref(spec), _ptr(coeffs, torch.float64), _ptr(stamps, torch.float32),
+            _ptr(bg, torch.float32)))
+
+    def subtract(self, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, diff,
+                 diff_var, diff_mask, chi2=None, n_chi2=None):
+        torch = self._torch
+        self._bind()
+        self._check(self.lib.argus_subtract(
+            self.h, _dims(ref), C.byref(spec), _ptr(stamps, torch.float32),
+            _ptr(bg, torch.float32), _ptr(ref, torch.float32), _ptr(ref_var, torch.float32),
+            _ptr(ref_mask, torch.uint8), _ptr(sci, torch.float32), _ptr(sci_var, torch.float32),
+            _ptr(sci_mask, torch.uint8), _ptr(diff, torch.float32),
+            _ptr(diff_var, torch.float32), _ptr(diff_mask, torch.uint8),
+            _ptr(chi2, torch.float64), _ptr(n_chi2, torch.int64)))
+
+    def detect(self, diff, diff_var, diff_mask, threshold, psf, psf_half, snr, det_mask, cands,
+               capacity, n_cands):
+        torch = self._torch
+        self._bind()
+        self._check(self.lib.argus_detect(
+            self.h, _dims(diff), _ptr(diff, torch.float32), _ptr(diff_var, torch.float32),
+            _ptr(diff_mask, torch.uint8), float(threshold), _ptr(psf, torch.float32),
+            int(psf_half), _ptr(snr, torch.float32), _ptr(det_mask, torch.uint8),
+            _ptr(cands, torch.uint8), int(capacity), _ptr(n_cands, torch.int32)))

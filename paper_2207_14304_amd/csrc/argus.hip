@@ -1,0 +1,266 @@
+// libargus C ABI: context, workspace, argument validation and dispatch.
+// The operations themselves are specified in include/argus.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.h"
+
+int argus_fail(argus_ctx *ctx, int code, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+static bool stream_capturing(argus_ctx *ctx) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+int argus_ws_reserve(argus_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return ARGUS_OK;
+    if (stream_capturing(ctx))
+        return argus_fail(ctx, ARGUS_EBUSY, "workspace of %zu bytes needed during stream capture", bytes);
+    if (ctx->ws) {
+        // work already queued may still read the old buffer
+        ARGUS_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+        ARGUS_HIP_CHECK(ctx, hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t want = bytes + (bytes >> 3);
+    if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+        ctx->ws = nullptr;
+        return argus_fail(ctx, ARGUS_ENOMEM, "workspace allocation of %zu bytes failed", want);
+    }
+    ctx->ws_bytes = want;
+    return ARGUS_OK;
+}
+
+void argus_time_begin(argus_ctx *ctx) {
+    if (ctx->timing) (void)hipEventRecord(ctx->ev0, ctx->stream);
+}
+
+void argus_time_end(argus_ctx *ctx, const char *name) {
+    if (!ctx->timing) return;
+    (void)hipEventRecord(ctx->ev1, ctx->stream);
+    (void)hipEventSynchronize(ctx->ev1);
+    float ms = -1.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    for (int i = 0; i < ctx->n_times; ++i)
+        if (ctx->times[i].name == name) { ctx->times[i].ms = ms; return; }
+    if (ctx->n_times < 16) ctx->times[ctx->n_times++] = {name, ms};
+}
+
+extern "C" {
+
+int argus_ctx_create(int device, argus_ctx **out) {
+    if (!out) return ARGUS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ARGUS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return ARGUS_EHIP;
+    argus_ctx *c = new argus_ctx();
+    c->device = device;
+    if (hipMalloc((void **)&c->tables, sizeof(BasisTables)) != hipSuccess) {
+        delete c;
+        return ARGUS_ENOMEM;
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        (void)hipFree(c->tables);
+        delete c;
+        return ARGUS_EHIP;
+    }
+    *out = c;
+    return ARGUS_OK;
+}
+
+void argus_ctx_destroy(argus_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->tables) (void)hipFree(ctx->tables);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+int argus_ctx_set_stream(argus_ctx *ctx, void *hip_stream) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->err.clear();
+    return ARGUS_OK;
+}
+
+const char *argus_last_error(const argus_ctx *ctx) { return ctx ? ctx->err.c_str() : "null ctx"; }
+
+int argus_ctx_set_timing(argus_ctx *ctx, int enable) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->timing = enable != 0;
+    ctx->n_times = 0;
+    return ARGUS_OK;
+}
+
+float argus_kernel_time_ms(argus_ctx *ctx, const char *kernel) {
+    if (!ctx || !kernel) return -1.f;
+    for (int i = 0; i < ctx->n_times; ++i)
+        if (ctx->times[i].name == kernel) return ctx->times[i].ms;
+    return -1.f;
+}
+
+static int check_dims(argus_ctx *ctx, argus_dims d) {
+    if (d.width < 1 || d.height < 1 || d.pitch < d.width)
+        return argus_fail(ctx, ARGUS_ESHAPE, "bad dims %dx%d pitch %lld", d.width, d.height,
+                          (long long)d.pitch);
+    if ((int64_t)d.height * d.pitch > ((int64_t)1 << 40))
+        return argus_fail(ctx, ARGUS_ESHAPE, "image too large");
+    return ARGUS_OK;
+}
+
+int argus_calibrate(argus_ctx *ctx, argus_dims dims, const uint16_t *raw, const float *dark,
+                    const float *flat, const uint8_t *bpm, float gain, float read_noise,
+                    uint16_t sat_adu, float *cal, float *var, uint8_t *mask) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (!raw || !dark || !flat || !cal || !mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate: null pointer");
+    if (!(gain > 0.f) || !(read_noise >= 0.f))
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate: gain must be > 0, read noise >= 0");
+    return launch_calibrate(ctx, dims, raw, dark, flat, bpm, gain, read_noise, sat_adu, cal, var,
+                            mask);
+}
+
+int argus_coadd(argus_ctx *ctx, argus_dims dims, int n_frames, const float *const *cal,
+                const float *const *var, const uint8_t *const *mask, float kappa, int max_iter,
+                float *ref, float *ref_var, uint8_t *ref_mask, uint8_t *n_used) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (n_frames < 1 || n_frames > ARGUS_MAX_FRAMES)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_coadd: n_frames %d not in 1..8", n_frames);
+    if (!cal || !var || !mask || !ref || !ref_var || !ref_mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_coadd: null pointer");
+    for (int i = 0; i < n_frames; ++i)
+        if (!cal[i] || !var[i] || !mask[i])
+            return argus_fail(ctx, ARGUS_EINVAL, "argus_coadd: null frame pointer %d", i);
+    if (!(kappa > 0.f) || max_iter < 0 || max_iter > 64)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_coadd: kappa > 0 and 0 <= max_iter <= 64");
+    return launch_coadd(ctx, dims, n_frames, cal, var, mask, kappa, max_iter, ref, ref_var,
+                        ref_mask, n_used);
+}
+
+static int check_spec(argus_ctx *ctx, const argus_kernel_spec *s) {
+    if (!s) return argus_fail(ctx, ARGUS_EINVAL, "null kernel spec");
+    if (s->n_gauss < 1 || s->n_gauss > 4)
+        return argus_fail(ctx, ARGUS_ESHAPE, "n_gauss %d not in 1..4", s->n_gauss);
+    for (int g = 0; g < s->n_gauss; ++g) {
+        if (!(s->sigma[g] > 0.0) || s->degree[g] < 0 || s->degree[g] > 6)
+            return argus_fail(ctx, ARGUS_ESHAPE, "gaussian %d: sigma > 0 and degree 0..6", g);
+    }
+    if (argus_nbasis(s) > ARGUS_MAX_NB)
+        return argus_fail(ctx, ARGUS_ESHAPE, "%d basis functions > %d", argus_nbasis(s), ARGUS_MAX_NB);
+    if (argus_nplanes(s) > ARGUS_MAX_PLANES)
+        return argus_fail(ctx, ARGUS_ESHAPE, "too many row-filter planes");
+    if (s->half_width < 1 || s->half_width > ARGUS_MAX_H)
+        return argus_fail(ctx, ARGUS_ESHAPE, "half_width %d not in 1..15", s->half_width);
+    if (s->spatial_degree < 0 || s->spatial_degree > ARGUS_MAX_D || s->bg_degree < 0 ||
+        s->bg_degree > s->spatial_degree)
+        return argus_fail(ctx, ARGUS_ESHAPE, "spatial_degree 0..2 and 0 <= bg_degree <= spatial_degree");
+    if (s->tiles_x < 1 || s->tiles_y < 1 || s->tiles_x > 4096 || s->tiles_y > 4096)
+        return argus_fail(ctx, ARGUS_ESHAPE, "tiles must be 1..4096 per axis");
+    if (s->mode != ARGUS_FIT_GLOBAL && s->mode != ARGUS_FIT_PER_TILE)
+        return argus_fail(ctx, ARGUS_EINVAL, "bad fit mode %d", s->mode);
+    if (s->precision != ARGUS_FP32 && s->precision != ARGUS_BF16X3)
+        return argus_fail(ctx, ARGUS_EINVAL, "bad precision %d", s->precision);
+    return ARGUS_OK;
+}
+
+int argus_kernel_dims(const argus_kernel_spec *spec, int *n_unknowns, int *n_solves) {
+    int rc = check_spec(nullptr, spec);
+    if (rc) return rc;
+    int n = argus_nbasis(spec) * argus_npoly(spec->spatial_degree) + argus_npoly(spec->bg_degree);
+    if (n_unknowns) *n_unknowns = n;
+    if (n_solves) *n_solves = spec->mode == ARGUS_FIT_GLOBAL ? 1 : spec->tiles_x * spec->tiles_y;
+    return ARGUS_OK;
+}
+
+int argus_fit_kernel(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
+                     const float *ref, const float *ref_var, const uint8_t *ref_mask,
+                     const float *sci, const float *sci_var, const uint8_t *sci_mask,
+                     double *coeffs, int64_t *n_fit, int32_t *status) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if ((rc = check_spec(ctx, spec))) return rc;
+    if (!ref || !ref_var || !ref_mask || !sci || !sci_var || !sci_mask || !coeffs || !status)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_fit_kernel: null pointer");
+    if (spec->tiles_x > dims.width || spec->tiles_y > dims.height)
+        return argus_fail(ctx, ARGUS_ESHAPE, "more tiles than pixels");
+    if ((rc = launch_basis_tables(ctx, spec))) return rc;
+    return launch_fit(ctx, dims, spec, ref, ref_var, ref_mask, sci, sci_var, sci_mask, coeffs,
+                      n_fit, status);
+}
+
+int argus_expand_kernel(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,
+                        float *stamps, float *bg) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_spec(ctx, spec);
+    if (rc) return rc;
+    if (!coeffs || !stamps || !bg) return argus_fail(ctx, ARGUS_EINVAL, "argus_expand_kernel: null pointer");
+    if ((rc = launch_basis_tables(ctx, spec))) return rc;
+    return launch_expand(ctx, spec, coeffs, stamps, bg);
+}
+
+int argus_subtract(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
+                   const float *stamps, const float *bg, const float *ref, const float *ref_var,
+                   const uint8_t *ref_mask, const float *sci, const float *sci_var,
+                   const uint8_t *sci_mask, float *diff, float *diff_var, uint8_t *diff_mask,
+                   double *chi2, int64_t *n_chi2) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if ((rc = check_spec(ctx, spec))) return rc;
+    if (!stamps || !bg || !ref || !ref_var || !ref_mask || !sci || !sci_var || !sci_mask ||
+        !diff || !diff_var || !diff_mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_subtract: null pointer");
+    if (spec->tiles_x > dims.width || spec->tiles_y > dims.height)
+        return argus_fail(ctx, ARGUS_ESHAPE, "more tiles than pixels");
+    return launch_subtract(ctx, dims, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var,
+                           sci_mask, diff, diff_var, diff_mask, chi2, n_chi2);
+}
+
+int argus_detect(argus_ctx *ctx, argus_dims dims, const float *diff, const float *diff_var,
+                 const uint8_t *diff_mask, float threshold, const float *psf, int psf_half,
+                 float *snr, uint8_t *det_mask, argus_candidate *cands, int32_t capacity,
+                 int32_t *n_cands) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (!diff || !diff_var || !diff_mask || !psf || !det_mask || !n_cands)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_detect: null pointer");
+    if (capacity < 0 || (capacity > 0 && !cands))
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_detect: capacity < 0 or null candidate list");
+    if (psf_half < 0 || psf_half > 15)
+        return argus_fail(ctx, ARGUS_ESHAPE, "psf_half %d not in 0..15", psf_half);
+    if (!(threshold == threshold))
+        return argus_fail(ctx, ARGUS_EINVAL, "threshold is NaN");
+    return launch_detect(ctx, dims, diff, diff_var, diff_mask, threshold, psf, psf_half, snr,
+                         det_mask, cands, capacity, n_cands);
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal declarations shared by the libargus translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "argus.h"
+
+// Largest supported shapes.
+#define ARGUS_MAX_H      15          // kernel half-width
+#define ARGUS_MAX_NB     31          // basis functions
+#define ARGUS_MAX_PLANES 16          // (gaussian, x-power) row-filter planes
+#define ARGUS_MAX_D      2           // spatial degree
+#define ARGUS_MAX_FRAMES 8           // coadd inputs
+
+// Device-resident basis tables, laid out in one buffer (floats unless noted).
+//   rowf [ARGUS_MAX_PLANES][32]  : exp(-u^2/2s^2) u^i, index u+h
+//   colf [32][32]                : alpha_k exp(-v^2/2s^2) v^j, index v+h
+//   gam  [32]                    : C'_k = conv_k + gam_k C'_0
+//   kpl  [32] (int)              : plane of basis k
+//   b2d  [32][31*31] (double)    : normalised 2-D basis B_k[v+h][u+h]
+struct BasisTables {
+    float rowf[ARGUS_MAX_PLANES][32];
+    float colf[32][32];
+    float gam[32];
+    int32_t kpl[32];
+    int32_t nb, nplanes, h, pad;
+    double b2d[32][31 * 31];
+};
+
+struct argus_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // workspace grown on demand
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // basis tables for the last spec seen
+    BasisTables *tables = nullptr;
+    bool tables_valid = false;
+    argus_kernel_spec tables_spec{};
+    // optional per-kernel timing
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::string last_kernel;
+    struct Timed { std::string name; float ms; };
+    Timed times[16];
+    int n_times = 0;
+};
+
+// ---- helpers implemented in argus.hip --------------------------------------
+int argus_fail(argus_ctx *ctx, int code, const char *fmt, ...);
+int argus_ws_reserve(argus_ctx *ctx, size_t bytes);
+void argus_time_begin(argus_ctx *ctx);
+void argus_time_end(argus_ctx *ctx, const char *name);
+
+// ---- spec helpers -----------------------------------------------------------
+static inline int argus_npoly(int D) { return (D + 1) * (D + 2) / 2; }
+static inline int argus_nbasis(const argus_kernel_spec *s) {
+    int nb = 0;
+    for (int g = 0; g < s->n_gauss; ++g) nb += (s->degree[g] + 1) * (s->degree[g] + 2) / 2;
+    return nb;
+}
+static inline int argus_nplanes(const argus_kernel_spec *s) {
+    int np = 0;
+    for (int g = 0; g < s->n_gauss; ++g) np += s->degree[g] + 1;
+    return np;
+}
+
+// ---- kernel launchers (one per translation unit) ----------------------------
+int launch_calibrate(argus_ctx *ctx, argus_dims d, const uint16_t *raw, const float *dark,
+                     const float *flat, const uint8_t *bpm, float gain, float rn,
+                     uint16_t sat, float *cal, float *var, uint8_t *mask);
+int launch_coadd(argus_ctx *ctx, argus_dims d, int n, const float *const *cal,
+                 const float *const *var, const uint8_t *const *mask, float kappa,
+                 int max_iter, float *ref, float *ref_var, uint8_t *ref_mask,
+                 uint8_t *n_used);
+int launch_basis_tables(argus_ctx *ctx, const argus_kernel_spec *spec);
+int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
+               const float *ref, const float *ref_var, const uint8_t *ref_mask,
+               const float *sci, const float *sci_var, const uint8_t *sci_mask,
+               double *coeffs, int64_t *n_fit, int32_t *status);
+int launch_expand(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,
+                  float *stamps, float *bg);
+int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
+                    const float *stamps, const float *bg, const float *ref,
+                    const float *ref_var, const uint8_t *ref_mask, const float *sci,
+                    const float *sci_var, const uint8_t *sci_mask, float *diff,
+                    float *diff_var, uint8_t *diff_mask, double *chi2, int64_t *n_chi2);
+int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
+                  const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
+                  uint8_t *det, argus_candidate *cands, int32_t cap, int32_t *n_cands);
+
+#define ARGUS_HIP_CHECK(ctx, call)                                                 \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return argus_fail((ctx), ARGUS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)

@@ -1,0 +1,779 @@
+// Kernel fit: basis tables, fused basis convolution + normal-equation
+// accumulation on MFMA, FP64 reduction of the partial sums, and the
+// Jacobi-scaled FP64 Cholesky solve.
+//
+// Model (Alard & Lupton 1998; Alard 2000): the design row of pixel p is
+//   X_p = [P_m(p) C_k(p)]_{k<nb, m<nP} ++ [P_m(p)]_{m<nPbg},
+// with C_k = ref (x) B_k.  Every entry of A = sum w X X^T is a moment
+//   G_{ab}[k][l] = sum_p w_p xt^a yt^b c_k(p) c_l(p),   a+b <= 2D,
+// of the 32-vector c = (C_0..C_{nb-1}, 1, 0...) (the 1 carries the
+// background), and b = sum w X S needs R_{ab}[k] = sum w xt^a yt^b c_k S,
+// a+b <= D.  Along one image row yt is constant, so a workgroup accumulates
+// only the xt-moments of the row on MFMA (FP32, 64 pixels) and then adds
+// yt^b times them into FP64 running sums: 2D+1 Gram blocks per pixel instead
+// of (2D+1)(2D+2)/2.
+#include "internal.h"
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int SW = 64;        // output columns per workgroup strip
+constexpr int CST = 33;       // LDS row stride of the 32-vector c (bank spread)
+constexpr int NTHR = 256;
+
+// ---------------------------------------------------------------------------
+// Basis tables, computed on the device in FP64 from the spec.
+// B_k(u,v) = exp(-(u^2+v^2)/2s^2) u^i v^j; B_0 -> unit sum; k>=1 with i, j
+// even -> B_k - (sum B_k) B_0; k >= 1 -> unit L2 norm.  In separable form
+// B'_k = alpha_k f_{g,i}(u) f_{g,j}(v) + beta_k B_0raw.
+__global__ void basis_tables_kernel(argus_kernel_spec s, BasisTables *T) {
+    __shared__ int kg[32], ki[32], kj[32], kp[32];
+    __shared__ double alpha[32], beta[32];
+    __shared__ double S0;
+    const int h = s.half_width, K = 2 * h + 1;
+    if (threadIdx.x == 0) {
+        int k = 0, p = 0;
+        for (int g = 0; g < s.n_gauss; ++g)
+            for (int i = 0; i <= s.degree[g]; ++i, ++p)
+                for (int j = 0; j <= s.degree[g] - i; ++j, ++k) {
+                    kg[k] = g; ki[k] = i; kj[k] = j; kp[k] = p;
+                }
+        T->nb = k;
+        T->nplanes = p;
+        T->h = h;
+        double sum = 0.0;
+        double is2 = 1.0 / (2.0 * s.sigma[0] * s.sigma[0]);
+        for (int v = -h; v <= h; ++v)
+            for (int u = -h; u <= h; ++u) sum += exp(-(double)(u * u + v * v) * is2);
+        S0 = sum;
+    }
+    __syncthreads();
+    const int nb = T->nb;
+    int k = threadIdx.x;
+    if (k < nb) {
+        double is2 = 1.0 / (2.0 * s.sigma[kg[k]] * s.sigma[kg[k]]);
+        double is20 = 1.0 / (2.0 * s.sigma[0] * s.sigma[0]);
+        double raw_sum = 0.0;
+        for (int v = -h; v <= h; ++v)
+            for (int u = -h; u <= h; ++u)
+                raw_sum += exp(-(double)(u * u + v * v) * is2) * pow((double)u, ki[k]) *
+                           pow((double)v, kj[k]);
+        bool even = (ki[k] % 2 == 0) && (kj[k] % 2 == 0);
+        double c0 = (k >= 1 && even) ? raw_sum / S0 : 0.0;   // subtract c0 * B_0raw
+        double nrm = 0.0;
+        for (int v = -h; v <= h; ++v)
+            for (int u = -h; u <= h; ++u) {
+                double b = exp(-(double)(u * u + v * v) * is2) * pow((double)u, ki[k]) *
+                           pow((double)v, kj[k]) - c0 * exp(-(double)(u * u + v * v) * is20);
+                nrm += b * b;
+            }
+        double a, be;
+        if (k == 0) {
+            a = 1.0 / S0;
+            be = 0.0;
+        } else {
+            a = 1.0 / sqrt(nrm);
+            be = -c0 * a;
+        }
+        alpha[k] = a;
+        beta[k] = be;
+        T->gam[k] = (float)(be * S0);     // C'_k = alpha_k conv_k + (beta_k / alpha_0) C'_0
+        T->kpl[k] = kp[k];
+        for (int v = -h; v <= h; ++v)
+            T->colf[k][v + h] = (float)(a * exp(-(double)(v * v) * is2) * pow((double)v, kj[k]));
+    }
+    __syncthreads();
+    // 2-D normalised basis for the kernel expansion
+    for (int idx = threadIdx.x; idx < nb * K * K; idx += blockDim.x) {
+        int kk = idx / (K * K), t = idx % (K * K);
+        int v = t / K - h, u = t % K - h;
+        double is2 = 1.0 / (2.0 * s.sigma[kg[kk]] * s.sigma[kg[kk]]);
+        double is20 = 1.0 / (2.0 * s.sigma[0] * s.sigma[0]);
+        double b = exp(-(double)(u * u + v * v) * is2) * pow((double)u, ki[kk]) * pow((double)v, kj[kk]);
+        T->b2d[kk][t] = alpha[kk] * b + beta[kk] * exp(-(double)(u * u + v * v) * is20);
+    }
+    // row filters per plane (g, i)
+    if (threadIdx.x < 32) {
+        int p = threadIdx.x;
+        int pp = 0;
+        for (int g = 0; g < s.n_gauss; ++g)
+            for (int i = 0; i <= s.degree[g]; ++i, ++pp)
+                if (pp == p) {
+                    double is2 = 1.0 / (2.0 * s.sigma[g] * s.sigma[g]);
+                    for (int u = -h; u <= h; ++u)
+                        T->rowf[p][u + h] = (float)(exp(-(double)(u * u) * is2) * pow((double)u, i));
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+struct FitArgs {
+    const float *ref, *rvar, *sci, *svar;
+    const uint8_t *rmask, *smask;
+    const BasisTables *tab;
+    double *partials;
+    int64_t pitch;
+    int W, H, h, nb, nplanes;
+    int RX, RY;                // regions (1x1 for GLOBAL, tiles for PER_TILE)
+    int spt, rchunks;          // strips per region, row chunks per region
+    int stride;                // doubles per partial
+    double sx, sy;             // 2/(W-1), 2/(H-1) (0 for a 1-pixel axis)
+};
+
+__device__ __forceinline__ int qidx(int a, int b, int Dm) {   // a+b <= Dm, a outer
+    return a * (Dm + 1) - a * (a - 1) / 2 + b;
+}
+
+template <int D>
+struct FitShape {
+    static constexpr int NA = 2 * D + 1;                       // xt powers in the Gram
+    static constexpr int NQ = (2 * D + 1) * (2 * D + 2) / 2;   // Gram moments
+    static constexpr int NRA = D + 1;                          // xt powers in the rhs
+    static constexpr int NR = (D + 1) * (D + 2) / 2;           // rhs moments
+    static constexpr int NT = 3 * NA;                          // (a, block pair) tasks
+};
+
+// Per-wave MFMA work on one 64-pixel row: tasks t = WAVE, WAVE+4, ... with
+// a = t / 3 and block pair bp = t % 3 in {(0,0), (0,1), (1,1)}.
+template <int D, int WAVE>
+struct WaveGram {
+    static constexpr int NT = FitShape<D>::NT;
+    static constexpr int NTW = (NT - WAVE + 3) / 4;
+    static constexpr int NB = 2 * D + 1;
+    double F[NTW > 0 ? NTW : 1][NB][4];
+
+    __device__ void zero() {
+#pragma unroll
+        for (int j = 0; j < (NTW > 0 ? NTW : 1); ++j)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) F[j][b][r] = 0.0;
+    }
+
+    __device__ void row(const float *cvec, const float *wx, const double *ypw, int lane) {
+        if constexpr (NTW > 0) {
+            floatx4 acc[NTW];
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int col = lane & 15, pk = lane >> 4;
+#pragma unroll 4
+            for (int s = 0; s < SW / 4; ++s) {
+                const int p = 4 * s + pk;
+                const float c0 = cvec[p * CST + col];
+                const float c1 = cvec[p * CST + 16 + col];
+#pragma unroll
+                for (int j = 0; j < NTW; ++j) {
+                    const int t = WAVE + 4 * j;
+                    const int a = t / 3, bp = t % 3;
+                    const float wa = wx[a * SW + p];
+                    const float A = (bp == 2) ? c1 : c0;
+                    const float B = wa * ((bp == 0) ? c0 : c1);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, B, acc[j], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                const int a = (WAVE + 4 * j) / 3;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b <= 2 * D - a) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) F[j][b][r] += ypw[b] * (double)acc[j][r];
+                    }
+                }
+            }
+        }
+    }
+
+    __device__ void store(double *part, int lane) {
+        if constexpr (NTW > 0) {
+            const int col = lane & 15, rb = 4 * (lane >> 4);
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                const int t = WAVE + 4 * j;
+                const int a = t / 3, bp = t % 3;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b <= 2 * D - a) {
+                        double *g = part + (size_t)qidx(a, b, 2 * D) * 768 + bp * 256;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) g[(rb + r) * 16 + col] = F[j][b][r];
+                    }
+                }
+            }
+        }
+    }
+};
+
+// LDS carve-up of the accumulation kernel (offsets in 4-byte words, then bytes).
+template <int D>
+struct FitLds {
+    float *rowf, *colf, *gam, *rowbuf, *inrow, *cvec, *wx, *wsx, *xtp;
+    int *kinfo;
+    uint8_t *mbuf, *minrow;
+    __host__ __device__ static size_t words(int nplanes, int K) {
+        using S = FitShape<D>;
+        return ARGUS_MAX_PLANES * 32 + 32 * 32 + 32 + (size_t)nplanes * K * SW + SW + 32 +
+               SW * CST + (S::NA + S::NRA) * SW + SW + 32;
+    }
+    __device__ FitLds(float *lds, int nplanes, int K) {
+        using S = FitShape<D>;
+        rowf = lds;                                     // [16][32]
+        colf = rowf + ARGUS_MAX_PLANES * 32;            // [32][32]
+        gam = colf + 32 * 32;                           // [32]
+        rowbuf = gam + 32;                              // [NPL][K][SW] circular rows
+        inrow = rowbuf + (size_t)nplanes * K * SW;      // [SW + 2h], padded to SW + 32
+        cvec = inrow + SW + 32;                         // [SW][CST]
+        wx = cvec + SW * CST;                           // [NA][SW]
+        wsx = wx + S::NA * SW;                          // [NRA][SW]
+        xtp = wsx + S::NRA * SW;                        // [SW]
+        kinfo = (int *)(xtp + SW);                      // [16] first k, [16] count
+        mbuf = (uint8_t *)(kinfo + 32);                 // [K][SW]
+        minrow = mbuf + (size_t)K * SW;                 // [SW + 32]
+    }
+};
+
+template <int D, int WAVE>
+__device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0, int ry1,
+                         bool active, double *part) {
+    using S = FitShape<D>;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int h = a.h, K = 2 * h + 1, NPL = a.nplanes, nb = a.nb;
+    FitLds<D> L(lds, NPL, K);
+    float *rowf = L.rowf, *colf = L.colf, *gam = L.gam, *rowbuf = L.rowbuf, *inrow = L.inrow;
+    float *cvec = L.cvec, *wx = L.wx, *wsx = L.wsx, *xtp = L.xtp;
+    int *kinfo = L.kinfo;
+    uint8_t *mbuf = L.mbuf, *minrow = L.minrow;
+    double *rhsbuf = (double *)rowbuf;                  // reused at the end
+
+    WaveGram<D, WAVE> gram;
+    gram.zero();
+    double RF[S::NR];
+#pragma unroll
+    for (int i = 0; i < S::NR; ++i) RF[i] = 0.0;
+    int count = 0;
+
+    const int64_t P = a.pitch;
+    const int yend = active ? ry1 + h : ry0 - h;
+    for (int yy = ry0 - h; yy < yend; ++yy) {
+        // P1: input row yy, columns sx0-h .. sx0+SW+h-1 (0 outside the image)
+        for (int j = tid; j < SW + 2 * h; j += NTHR) {
+            int X = sx0 - h + j;
+            bool in = X >= 0 && X < a.W;
+            inrow[j] = in ? a.ref[(int64_t)yy * P + X] : 0.f;
+            minrow[j] = in ? (a.rmask[(int64_t)yy * P + X] != 0) : 0;
+        }
+        __syncthreads();
+        // P2: row filters for every plane; row-OR of the reference mask
+        const int slot = yy % K;
+        for (int it = tid; it < NPL * SW; it += NTHR) {
+            int p = it / SW, x = it % SW;
+            const float *f = rowf + p * 32;
+            float acc = 0.f;
+            for (int uu = 0; uu < K; ++uu) acc += f[uu] * inrow[x + 2 * h - uu];
+            rowbuf[(p * K + slot) * SW + x] = acc;
+        }
+        if (tid < SW) {
+            uint8_t m = 0;
+            for (int uu = 0; uu < K; ++uu) m |= minrow[tid + uu];
+            mbuf[slot * SW + tid] = m;
+        }
+        __syncthreads();
+        if (yy < ry0 + h) continue;
+        const int y = yy - h;
+        // P3: column filters -> raw separable convolutions in cvec
+        for (int it = tid; it < NPL * SW; it += NTHR) {
+            int p = it / SW, x = it % SW;
+            int k0 = kinfo[p], nk = kinfo[16 + p];
+            float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int vv = 0; vv < K; ++vv) {
+                int row = y + h - vv;
+                float t = rowbuf[(p * K + row % K) * SW + x];
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    if (q < nk) acc[q] += colf[(k0 + q) * 32 + vv] * t;
+            }
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (q < nk) cvec[x * CST + k0 + q] = acc[q];
+        }
+        // fit-set weights of this output row
+        if (tid < SW) {
+            const int X = sx0 + tid;
+            float w = 0.f, Sv = 0.f;
+            if (X < sx1) {
+                uint8_t foot = 0;
+                for (int q = 0; q < K; ++q) foot |= mbuf[q * SW + tid];
+                int64_t o = (int64_t)y * P + X;
+                float sv = a.svar[o], rv = a.rvar[o];
+                Sv = a.sci[o];
+                float tot = sv + rv;
+                if (a.smask[o] == 0 && foot == 0 && tot > 0.f) {
+                    w = 1.0f / tot;
+                    ++count;
+                }
+            }
+            float xt = xtp[tid], xp = 1.f;
+#pragma unroll
+            for (int e = 0; e < S::NA; ++e) {
+                wx[e * SW + tid] = w * xp;
+                if (e < S::NRA) wsx[e * SW + tid] = w * Sv * xp;
+                xp *= xt;
+            }
+        }
+        __syncthreads();
+        // P4: flux-normalised combination C'_k += gam_k C'_0
+        for (int it = tid; it < SW * nb; it += NTHR) {
+            int x = it / nb, k = it % nb;
+            float g = gam[k];
+            if (k > 0 && g != 0.f) cvec[x * CST + k] += g * cvec[x * CST];
+        }
+        __syncthreads();
+        // P5: MFMA Gram moments of this row and VALU right-hand side
+        double ypw[2 * D + 1];
+        {
+            double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
+            double yp = 1.0;
+#pragma unroll
+            for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
+        }
+        gram.row(cvec, wx, ypw, lane);
+        {
+            const int k = lane & 31, half = lane >> 5;
+            float ra[S::NRA];
+#pragma unroll
+            for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int px = WAVE * 16 + half * 8 + i;
+                const float c = cvec[px * CST + k];
+#pragma unroll
+                for (int e = 0; e < S::NRA; ++e) ra[e] += wsx[e * SW + px] * c;
+            }
+#pragma unroll
+            for (int e = 0; e < S::NRA; ++e)
+#pragma unroll
+                for (int b = 0; b <= D; ++b)
+                    if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
+        }
+    }
+    __syncthreads();
+    // Gram partials: every (moment, block pair) element is written by one lane
+    gram.store(part, lane);
+    // rhs: 8 half-wave partials per (moment, k), summed in a fixed order
+    {
+        const int k = lane & 31, half = lane >> 5;
+#pragma unroll
+        for (int i = 0; i < S::NR; ++i) rhsbuf[((WAVE * 2 + half) * S::NR + i) * 32 + k] = RF[i];
+    }
+    // fit-pixel count (wave 0 holds it)
+    if (WAVE == 0) {
+        double c = (double)count;
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if (lane == 0) part[(size_t)S::NQ * 768 + S::NR * 32] = c;
+    }
+    __syncthreads();
+    for (int it = tid; it < S::NR * 32; it += NTHR) {
+        double s = 0.0;
+        for (int q = 0; q < 8; ++q) s += rhsbuf[q * S::NR * 32 + it];
+        part[(size_t)S::NQ * 768 + it] = s;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(NTHR) void fit_accum_kernel(FitArgs a) {
+    extern __shared__ float lds[];
+    const int tid = threadIdx.x;
+    // workgroup -> region, strip, row chunk
+    const int s = blockIdx.x % a.spt, rx = blockIdx.x / a.spt;
+    const int rc = blockIdx.y % a.rchunks, ry = blockIdx.y / a.rchunks;
+    const int rx0 = (int)((int64_t)rx * a.W / a.RX), rx1 = (int)((int64_t)(rx + 1) * a.W / a.RX);
+    const int ry0g = (int)((int64_t)ry * a.H / a.RY), ry1g = (int)((int64_t)(ry + 1) * a.H / a.RY);
+    const int ix0 = max(rx0, a.h), ix1 = min(rx1, a.W - a.h);
+    const int iy0 = max(ry0g, a.h), iy1 = min(ry1g, a.H - a.h);
+    int sx0 = ix0 + s * SW, sx1 = min(sx0 + SW, ix1);
+    int rows = max(iy1 - iy0, 0);
+    int rh = (rows + a.rchunks - 1) / a.rchunks;
+    int ry0 = iy0 + rc * rh, ry1 = min(ry0 + rh, iy1);
+    const bool active = sx0 < sx1 && ry0 < ry1;    // otherwise the partial is all zeros
+    const int pid = ((ry * a.RX + rx) * a.rchunks + rc) * a.spt + s;
+    double *part = a.partials + (size_t)pid * a.stride;
+
+    // stage the filter tables and per-strip constants
+    const int K = 2 * a.h + 1;
+    FitLds<D> L(lds, a.nplanes, K);
+    float *rowf = L.rowf, *colf = L.colf, *gam = L.gam, *xtp = L.xtp, *cvec = L.cvec;
+    int *kinfo = L.kinfo;
+    for (int i = tid; i < ARGUS_MAX_PLANES * 32; i += NTHR) rowf[i] = (&a.tab->rowf[0][0])[i];
+    for (int i = tid; i < 32 * 32; i += NTHR) colf[i] = (&a.tab->colf[0][0])[i];
+    if (tid < 32) gam[tid] = tid < a.nb ? a.tab->gam[tid] : 0.f;
+    if (tid < SW) {
+        int X = sx0 + tid;
+        xtp[tid] = (float)((double)X * a.sx - (a.sx != 0.0 ? 1.0 : 0.0));
+    }
+    if (tid == 0) {
+        for (int p = 0; p < 16; ++p) { kinfo[p] = 0; kinfo[16 + p] = 0; }
+        for (int k = 0; k < a.nb; ++k) {
+            int p = a.tab->kpl[k];
+            if (kinfo[16 + p] == 0) kinfo[p] = k;
+            kinfo[16 + p]++;
+        }
+    }
+    // constant tail of c: 1 at index nb (background), zeros after
+    for (int i = tid; i < SW * CST; i += NTHR) {
+        int k = i % CST;
+        cvec[i] = (k == a.nb) ? 1.f : 0.f;
+    }
+    __syncthreads();
+    switch (tid >> 6) {
+        case 0: fit_wave<D, 0>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        case 1: fit_wave<D, 1>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        case 2: fit_wave<D, 2>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        default: fit_wave<D, 3>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+    }
+}
+
+// Sum consecutive groups of partial vectors in a fixed order (deterministic).
+__global__ void sum_parts_kernel(const double *in, int stride, int n_in, int group, double *out) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    int set = blockIdx.y;
+    if (e >= stride) return;
+    int j0 = set * group, j1 = min(j0 + group, n_in);
+    double s = 0.0;
+    for (int j = j0; j < j1; ++j) s += in[(size_t)j * stride + e];
+    out[(size_t)set * stride + e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Solve: assemble A and b from the moments, Jacobi scale, right-looking
+// Cholesky on the packed lower triangle, two triangular solves.
+struct SolveArgs {
+    const double *sums;        // [n_solves][stride]
+    int stride;
+    int nb, D, Dbg, n;
+    double *coeffs;
+    int64_t *n_fit;
+    int32_t *status;
+    double *gtri;              // global fallback storage for the factor (or null)
+};
+
+__device__ __forceinline__ void unpack_row(int r, int nb, int D, int Dbg, int &k, int &p, int &q) {
+    int nP = (D + 1) * (D + 2) / 2;
+    int m;
+    int Dm;
+    if (r < nb * nP) { k = r / nP; m = r % nP; Dm = D; }
+    else { k = nb; m = r - nb * nP; Dm = Dbg; }
+    // monomial m of degree <= Dm: p outer, q inner
+    int pp = 0;
+    while (m > Dm - pp) { m -= Dm - pp + 1; ++pp; }
+    p = pp;
+    q = m;
+}
+
+__device__ __forceinline__ double gram_at(const double *G, int q, int k, int l) {
+    // G[q][bp][16][16], blocks (0,0), (0,1), (1,1) of the symmetric 32x32 moment
+    if (k > l) { int t = k; k = l; l = t; }
+    const double *g = G + (size_t)q * 768;
+    if (l < 16) return g[k * 16 + l];
+    if (k < 16) return g[256 + k * 16 + (l - 16)];
+    return g[512 + (k - 16) * 16 + (l - 16)];
+}
+
+__device__ double block_sum(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+
+__global__ __launch_bounds__(NTHR) void fit_solve_kernel(SolveArgs a) {
+    extern __shared__ double sl[];
+    const int n = a.n, tid = threadIdx.x, sol = blockIdx.x;
+    const int ntri = n * (n + 1) / 2;
+    double *L = a.gtri ? a.gtri + (size_t)sol * ntri : sl;
+    double *bb = sl + (a.gtri ? 0 : ntri);
+    double *dd = bb + n;
+    double *red = dd + n;                 // [8]
+    __shared__ int bad;
+    const double *sums = a.sums + (size_t)sol * a.stride;
+    const int D = a.D, NQ = (2 * D + 1) * (2 * D + 2) / 2;
+    const double cnt = sums[(size_t)NQ * 768 + (D + 1) * (D + 2) / 2 * 32];
+    double *co = a.coeffs + (size_t)sol * n;
+    if (tid == 0) {
+        bad = 0;
+        if (a.n_fit) a.n_fit[sol] = (int64_t)cnt;
+    }
+    if (cnt < (double)n) {
+        for (int i = tid; i < n; i += NTHR) co[i] = __builtin_nan("");
+        if (tid == 0) a.status[sol] = ARGUS_ETOOFEW;
+        return;
+    }
+    // assemble packed lower triangle and rhs
+    for (int idx = tid; idx < ntri; idx += NTHR) {
+        int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+        while (r * (r + 1) / 2 > idx) --r;
+        int c = idx - r * (r + 1) / 2;
+        int kr, pr, qr, kc, pc, qc;
+        unpack_row(r, a.nb, D, a.Dbg, kr, pr, qr);
+        unpack_row(c, a.nb, D, a.Dbg, kc, pc, qc);
+        L[idx] = gram_at(sums, qidx(pr + pc, qr + qc, 2 * D), kr, kc);
+    }
+    for (int r = tid; r < n; r += NTHR) {
+        int k, p, q;
+        unpack_row(r, a.nb, D, a.Dbg, k, p, q);
+        bb[r] = sums[(size_t)NQ * 768 + qidx(p, q, D) * 32 + k];
+    }
+    __syncthreads();
+    for (int r = tid; r < n; r += NTHR) {
+        double dg = L[r * (r + 1) / 2 + r];
+        if (!(dg > 0.0)) bad = 1;
+        dd[r] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
+    }
+    __syncthreads();
+    if (bad) {
+        for (int i = tid; i < n; i += NTHR) co[i] = __builtin_nan("");
+        if (tid == 0) a.status[sol] = ARGUS_ESINGULAR;
+        return;
+    }
+    for (int idx = tid; idx < ntri; idx += NTHR) {
+        int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+        while (r * (r + 1) / 2 > idx) --r;
+        int c = idx - r * (r + 1) / 2;
+        L[idx] *= dd[r] * dd[c];
+    }
+    for (int r = tid; r < n; r += NTHR) bb[r] *= dd[r];
+    __syncthreads();
+    double mx = 0.0;
+    for (int r = tid; r < n; r += NTHR) mx = fmax(mx, L[r * (r + 1) / 2 + r]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    double maxdiag = 0.0;
+    for (int i = 0; i < NTHR / 64; ++i) maxdiag = fmax(maxdiag, red[i]);
+    const double tol = (double)n * 0x1p-52 * maxdiag;
+    __syncthreads();
+    // right-looking Cholesky
+    for (int j = 0; j < n; ++j) {
+        double piv = L[j * (j + 1) / 2 + j];
+        if (!(piv > tol)) {
+            if (tid == 0) bad = 1;
+            break;
+        }
+        double ljj = sqrt(piv);
+        __syncthreads();
+        for (int i = j + 1 + tid; i < n; i += NTHR) L[i * (i + 1) / 2 + j] /= ljj;
+        if (tid == 0) L[j * (j + 1) / 2 + j] = ljj;
+        __syncthreads();
+        // trailing update of rows i > j, columns j < c <= i
+        const int m = n - j - 1;
+        const int nupd = m * (m + 1) / 2;
+        for (int idx = tid; idx < nupd; idx += NTHR) {
+            int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+            while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+            while (r * (r + 1) / 2 > idx) --r;
+            int c = idx - r * (r + 1) / 2;
+            int i = j + 1 + r, cc = j + 1 + c;
+            L[i * (i + 1) / 2 + cc] -= L[i * (i + 1) / 2 + j] * L[cc * (cc + 1) / 2 + j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        for (int i = tid; i < n; i += NTHR) co[i] = __builtin_nan("");
+        if (tid == 0) a.status[sol] = ARGUS_ESINGULAR;
+        return;
+    }
+    // forward and back substitution (wave 0)
+    if (tid < 64) {
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int k = tid; k < i; k += 64) s += L[i * (i + 1) / 2 + k] * bb[k];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            double v = (bb[i] - s) / L[i * (i + 1) / 2 + i];
+            __builtin_amdgcn_wave_barrier();
+            bb[i] = v;      // every lane stores the same value, so each lane sees it
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int k = i + 1 + tid; k < n; k += 64) s += L[k * (k + 1) / 2 + i] * bb[k];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            double v = (bb[i] - s) / L[i * (i + 1) / 2 + i];
+            __builtin_amdgcn_wave_barrier();
+            bb[i] = v;
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int i = tid; i < n; i += 64) co[i] = dd[i] * bb[i];
+        if (tid == 0) a.status[sol] = ARGUS_OK;
+    }
+}
+
+// K_m = sum_k a_{k nP + m} B_k (FP64), bg_m = a_{nb nP + m}
+__global__ void expand_kernel(const BasisTables *T, const double *coeffs, int n, int nP, int nPb,
+                              float *stamps, float *bg) {
+    const int s = blockIdx.x / nP, m = blockIdx.x % nP;
+    const int K = 2 * T->h + 1, nb = T->nb;
+    const double *a = coeffs + (size_t)s * n;
+    for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
+        double acc = 0.0;
+        for (int k = 0; k < nb; ++k) acc += a[k * nP + m] * T->b2d[k][t];
+        stamps[((size_t)s * nP + m) * K * K + t] = (float)acc;
+    }
+    if (threadIdx.x == 0 && m < nPb) bg[(size_t)s * nPb + m] = (float)a[nb * nP + m];
+}
+
+template <int D>
+size_t fit_lds_bytes(int h, int nplanes) {
+    using S = FitShape<D>;
+    int K = 2 * h + 1;
+    size_t bytes = FitLds<D>::words(nplanes, K) * 4 + (size_t)K * SW + SW + 32;
+    size_t rhs = (size_t)8 * S::NR * 32 * 8;          // reuses rowbuf at the end
+    size_t rowbuf_bytes = (size_t)nplanes * K * SW * 4;
+    if (rhs > rowbuf_bytes) bytes += rhs - rowbuf_bytes;
+    return (bytes + 15) & ~(size_t)15;
+}
+
+template <int D>
+int fit_launch_d(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, FitArgs &fa,
+                 int n_regions, int parts_per_region, double **sums_out) {
+    using S = FitShape<D>;
+    fa.stride = S::NQ * 768 + S::NR * 32 + 1;
+    fa.stride = (fa.stride + 1) & ~1;
+    const int n_parts = n_regions * parts_per_region;
+    const int group = 64;
+    const int n_g1 = spec->mode == ARGUS_FIT_GLOBAL ? (n_parts + group - 1) / group : 0;
+    const int n = fa.nb * argus_npoly(D) + argus_npoly(spec->bg_degree);
+    size_t need = ((size_t)n_parts + n_g1 + n_regions) * fa.stride * sizeof(double) +
+                  (size_t)n * (n + 1) / 2 * sizeof(double) * n_regions;
+    int rc = argus_ws_reserve(ctx, need + 256);
+    if (rc) return rc;
+    double *base = (double *)ctx->ws;
+    fa.partials = base;
+    double *stage1 = base + (size_t)n_parts * fa.stride;
+    double *sums = stage1 + (size_t)n_g1 * fa.stride;
+    size_t lds = fit_lds_bytes<D>(fa.h, fa.nplanes);
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)fit_accum_kernel<D>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    dim3 grid(fa.RX * fa.spt, fa.RY * fa.rchunks);
+    argus_time_begin(ctx);
+    hipLaunchKernelGGL(fit_accum_kernel<D>, grid, dim3(NTHR), lds, ctx->stream, fa);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, "fit_accum");
+    argus_time_begin(ctx);
+    dim3 rb((fa.stride + 255) / 256);
+    if (spec->mode == ARGUS_FIT_GLOBAL) {
+        hipLaunchKernelGGL(sum_parts_kernel, dim3(rb.x, n_g1), dim3(256), 0, ctx->stream,
+                           (const double *)fa.partials, fa.stride, n_parts, group, stage1);
+        hipLaunchKernelGGL(sum_parts_kernel, dim3(rb.x, 1), dim3(256), 0, ctx->stream,
+                           (const double *)stage1, fa.stride, n_g1, n_g1, sums);
+    } else {
+        hipLaunchKernelGGL(sum_parts_kernel, dim3(rb.x, n_regions), dim3(256), 0, ctx->stream,
+                           (const double *)fa.partials, fa.stride, n_parts, parts_per_region, sums);
+    }
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, "fit_reduce");
+    *sums_out = sums;
+    return ARGUS_OK;
+}
+
+}  // namespace
+
+int launch_basis_tables(argus_ctx *ctx, const argus_kernel_spec *spec) {
+    const argus_kernel_spec &o = ctx->tables_spec;
+    bool same = ctx->tables_valid && o.n_gauss == spec->n_gauss && o.half_width == spec->half_width;
+    for (int g = 0; same && g < spec->n_gauss; ++g)
+        same = o.sigma[g] == spec->sigma[g] && o.degree[g] == spec->degree[g];
+    if (same) return ARGUS_OK;
+    hipLaunchKernelGGL(basis_tables_kernel, dim3(1), dim3(256), 0, ctx->stream, *spec, ctx->tables);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    ctx->tables_spec = *spec;
+    ctx->tables_valid = true;
+    return ARGUS_OK;
+}
+
+int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, const float *ref,
+               const float *ref_var, const uint8_t *ref_mask, const float *sci,
+               const float *sci_var, const uint8_t *sci_mask, double *coeffs, int64_t *n_fit,
+               int32_t *status) {
+    FitArgs fa;
+    fa.ref = ref; fa.rvar = ref_var; fa.sci = sci; fa.svar = sci_var;
+    fa.rmask = ref_mask; fa.smask = sci_mask;
+    fa.tab = ctx->tables;
+    fa.pitch = d.pitch; fa.W = d.width; fa.H = d.height;
+    fa.h = spec->half_width;
+    fa.nb = argus_nbasis(spec);
+    fa.nplanes = argus_nplanes(spec);
+    const bool global = spec->mode == ARGUS_FIT_GLOBAL;
+    fa.RX = global ? 1 : spec->tiles_x;
+    fa.RY = global ? 1 : spec->tiles_y;
+    int maxw = (d.width + fa.RX - 1) / fa.RX;
+    int maxh = (d.height + fa.RY - 1) / fa.RY;
+    fa.spt = (maxw + SW - 1) / SW;
+    // enough workgroups to fill the chip, without row chunks shorter than 8h
+    int base = fa.RX * fa.RY * fa.spt;
+    int want = (2048 + base - 1) / base;
+    int maxc = maxh / (8 * fa.h) > 1 ? maxh / (8 * fa.h) : 1;
+    fa.rchunks = want < 1 ? 1 : (want > maxc ? maxc : want);
+    fa.sx = d.width > 1 ? 2.0 / (d.width - 1) : 0.0;
+    fa.sy = d.height > 1 ? 2.0 / (d.height - 1) : 0.0;
+    const int n_regions = fa.RX * fa.RY;
+    const int parts_per_region = fa.rchunks * fa.spt;
+    double *sums = nullptr;
+    int rc;
+    switch (spec->spatial_degree) {
+        case 0: rc = fit_launch_d<0>(ctx, d, spec, fa, n_regions, parts_per_region, &sums); break;
+        case 1: rc = fit_launch_d<1>(ctx, d, spec, fa, n_regions, parts_per_region, &sums); break;
+        default: rc = fit_launch_d<2>(ctx, d, spec, fa, n_regions, parts_per_region, &sums); break;
+    }
+    if (rc) return rc;
+    SolveArgs sa;
+    sa.sums = sums;
+    sa.stride = fa.stride;
+    sa.nb = fa.nb;
+    sa.D = spec->spatial_degree;
+    sa.Dbg = spec->bg_degree;
+    sa.n = fa.nb * argus_npoly(sa.D) + argus_npoly(sa.Dbg);
+    sa.coeffs = coeffs;
+    sa.n_fit = n_fit;
+    sa.status = status;
+    sa.gtri = nullptr;
+    size_t lds = ((size_t)sa.n * (sa.n + 1) / 2 + 2 * sa.n + 8) * sizeof(double);
+    int dev_max = 0;
+    ARGUS_HIP_CHECK(ctx, hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                               ctx->device));
+    if (lds > (size_t)dev_max) {
+        // factor in global memory (after the sums in the workspace)
+        size_t tri = (size_t)sa.n * (sa.n + 1) / 2 * sizeof(double) * n_regions;
+        size_t used = (size_t)((char *)(sums + (size_t)n_regions * fa.stride) - (char *)ctx->ws);
+        if (used + tri > ctx->ws_bytes)
+            return argus_fail(ctx, ARGUS_ENOMEM, "solve storage does not fit the workspace");
+        sa.gtri = sums + (size_t)n_regions * fa.stride;
+        lds = ((size_t)2 * sa.n + 8) * sizeof(double);
+    }
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)fit_solve_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    argus_time_begin(ctx);
+    hipLaunchKernelGGL(fit_solve_kernel, dim3(n_regions), dim3(NTHR), lds, ctx->stream, sa);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, "fit_solve");
+    return ARGUS_OK;
+}
+
+int launch_expand(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,
+                  float *stamps, float *bg) {
+    int n, ns;
+    argus_kernel_dims(spec, &n, &ns);
+    int nP = argus_npoly(spec->spatial_degree), nPb = argus_npoly(spec->bg_degree);
+    hipLaunchKernelGGL(expand_kernel, dim3(ns * nP), dim3(256), 0, ctx->stream,
+                       (const BasisTables *)ctx->tables, coeffs, n, nP, nPb, stamps, bg);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    return ARGUS_OK;
+}

@@ -1,0 +1,287 @@
+// Streaming per-pixel kernels: calibration and the clipped-mean reference coadd.
+// Both are HBM-bound; each thread owns 8 (calibrate) or 4 (coadd) consecutive
+// pixels of one row so that every plane is read with 8- or 16-byte vector
+// loads, and rows with a pitch are handled by a (row, chunk) mapping.
+#include "internal.h"
+
+namespace {
+
+constexpr int CAL_PX = 8;
+constexpr int CO_PX = 4;
+
+struct CalArgs {
+    const uint16_t *raw;
+    const float *dark, *flat;
+    const uint8_t *bpm;
+    float *cal, *var;
+    uint8_t *mask;
+    int64_t pitch;
+    int W, H, chunks;         // chunks of CAL_PX pixels per row
+    double inv_g, rn2_g2;
+    float sat;
+    int vec;                  // all planes 16-byte aligned for vector access
+};
+
+// cal = (raw - dark)/flat, var = (max(raw - dark, 0)/g + rn^2/g^2)/flat^2.
+// raw - dark is exact in FP64 (raw is an integer below 2^16, dark a float);
+// the divisions are correctly rounded FP64, so each output is the FP64 value
+// rounded once to FP32.
+__device__ __forceinline__ void cal_one(const CalArgs &a, uint16_t r, float d, float f,
+                                        uint8_t b, float &c, float &v, uint8_t &m) {
+    bool bad = (b != 0) || !(f > 0.f) || !__builtin_isfinite(f) || !__builtin_isfinite(d);
+    double sig = (double)r - (double)d;
+    double fd = (double)f;
+    double cd = sig / fd;
+    double vd = (fmax(sig, 0.0) * a.inv_g + a.rn2_g2) / (fd * fd);
+    c = bad ? 0.f : (float)cd;
+    v = bad ? 0.f : (float)vd;
+    m = (bad ? ARGUS_BAD : 0u) | ((float)r >= a.sat ? ARGUS_SAT : 0u);
+}
+
+__global__ __launch_bounds__(256) void calibrate_kernel(CalArgs a) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)a.H * a.chunks;
+    if (t >= total) return;
+    int y = (int)(t / a.chunks);
+    int x0 = (int)(t - (int64_t)y * a.chunks) * CAL_PX;
+    int64_t o = (int64_t)y * a.pitch + x0;
+    if (a.vec && x0 + CAL_PX <= a.W) {
+        uint4 r8 = *(const uint4 *)(a.raw + o);
+        float4 d0 = *(const float4 *)(a.dark + o), d1 = *(const float4 *)(a.dark + o + 4);
+        float4 f0 = *(const float4 *)(a.flat + o), f1 = *(const float4 *)(a.flat + o + 4);
+        uint2 b8 = a.bpm ? *(const uint2 *)(a.bpm + o) : make_uint2(0u, 0u);
+        uint16_t r[8];
+        r[0] = r8.x & 0xffff; r[1] = r8.x >> 16; r[2] = r8.y & 0xffff; r[3] = r8.y >> 16;
+        r[4] = r8.z & 0xffff; r[5] = r8.z >> 16; r[6] = r8.w & 0xffff; r[7] = r8.w >> 16;
+        float d[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        float f[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+        float c[8], v[8];
+        uint8_t m[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint8_t b = (uint8_t)(((i < 4 ? b8.x : b8.y) >> (8 * (i & 3))) & 0xff);
+            cal_one(a, r[i], d[i], f[i], b, c[i], v[i], m[i]);
+        }
+        *(float4 *)(a.cal + o) = make_float4(c[0], c[1], c[2], c[3]);
+        *(float4 *)(a.cal + o + 4) = make_float4(c[4], c[5], c[6], c[7]);
+        if (a.var) {
+            *(float4 *)(a.var + o) = make_float4(v[0], v[1], v[2], v[3]);
+            *(float4 *)(a.var + o + 4) = make_float4(v[4], v[5], v[6], v[7]);
+        }
+        uint2 mo;
+        mo.x = m[0] | (m[1] << 8) | (m[2] << 16) | ((uint32_t)m[3] << 24);
+        mo.y = m[4] | (m[5] << 8) | (m[6] << 16) | ((uint32_t)m[7] << 24);
+        *(uint2 *)(a.mask + o) = mo;
+        return;
+    }
+    int n = min(CAL_PX, a.W - x0);
+    for (int i = 0; i < n; ++i) {
+        float c, v;
+        uint8_t m;
+        cal_one(a, a.raw[o + i], a.dark[o + i], a.flat[o + i], a.bpm ? a.bpm[o + i] : 0, c, v, m);
+        a.cal[o + i] = c;
+        if (a.var) a.var[o + i] = v;
+        a.mask[o + i] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Clipped-mean coadd.  Decisions (medians, the clip test) are taken in FP64 on
+// the FP32 inputs; survivors are tracked as a bitmask per pixel.
+struct CoaddArgs {
+    const float *cal[ARGUS_MAX_FRAMES];
+    const float *var[ARGUS_MAX_FRAMES];
+    const uint8_t *mask[ARGUS_MAX_FRAMES];
+    float *ref, *ref_var;
+    uint8_t *ref_mask, *n_used;
+    int64_t pitch;
+    int W, H, chunks;
+    double kappa2;
+    int max_iter;
+    int vec;
+};
+
+// Sort the N values with non-survivors pushed to +inf (odd-even transposition).
+template <int N>
+__device__ __forceinline__ void sort_n(double (&s)[N]) {
+#pragma unroll
+    for (int pass = 0; pass < N; ++pass) {
+#pragma unroll
+        for (int i = pass & 1; i + 1 < N; i += 2) {
+            double lo = fmin(s[i], s[i + 1]), hi = fmax(s[i], s[i + 1]);
+            s[i] = lo;
+            s[i + 1] = hi;
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ double median_of(const float (&x)[N], unsigned S, int cnt) {
+    double s[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = (S >> i & 1u) ? (double)x[i] : __builtin_inf();
+    sort_n<N>(s);
+    int lo = (cnt - 1) >> 1, hi = cnt >> 1;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        a = (i == lo) ? s[i] : a;
+        b = (i == hi) ? s[i] : b;
+    }
+    return 0.5 * (a + b);
+}
+
+template <int N>
+__device__ __forceinline__ void coadd_one(const CoaddArgs &a, const float (&x)[N],
+                                          const float (&v)[N], const uint8_t (&m)[N], float &ref,
+                                          float &rv, uint8_t &rm, uint8_t &nu) {
+    unsigned S = 0u;
+    bool sat = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (!(m[i] & (ARGUS_BAD | ARGUS_SAT))) S |= 1u << i;
+        sat |= (m[i] & ARGUS_SAT) != 0;
+    }
+    unsigned S0 = S;
+    for (int it = 0; it < a.max_iter; ++it) {
+        int cnt = __builtin_popcount(S);
+        if (cnt <= 2) break;
+        double c = median_of<N>(x, S, cnt);
+        double s2 = median_of<N>(v, S, cnt);
+        double thr = a.kappa2 * s2;
+        unsigned rej = 0u;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double dd = (double)x[i] - c;
+            if ((S >> i & 1u) && dd * dd > thr) rej |= 1u << i;
+        }
+        int nr = __builtin_popcount(rej);
+        if (nr == 0 || cnt - nr < 2) break;
+        S &= ~rej;
+    }
+    int cnt = __builtin_popcount(S);
+    double sx = 0.0, sv = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (S >> i & 1u) {
+            sx += (double)x[i];
+            sv += (double)v[i];
+        }
+    }
+    ref = cnt ? (float)(sx / cnt) : 0.f;
+    rv = cnt ? (float)(sv / ((double)cnt * cnt)) : 0.f;
+    rm = (S0 == 0u ? ARGUS_NODATA : 0u) | (sat ? ARGUS_SAT : 0u);
+    nu = (uint8_t)cnt;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void coadd_kernel(CoaddArgs a) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)a.H * a.chunks;
+    if (t >= total) return;
+    int y = (int)(t / a.chunks);
+    int x0 = (int)(t - (int64_t)y * a.chunks) * CO_PX;
+    int64_t o = (int64_t)y * a.pitch + x0;
+    int n = min(CO_PX, a.W - x0);
+    float x[CO_PX][N], v[CO_PX][N];
+    uint8_t m[CO_PX][N];
+    if (a.vec && n == CO_PX) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float4 xc = *(const float4 *)(a.cal[i] + o);
+            float4 vc = *(const float4 *)(a.var[i] + o);
+            uint32_t mc = *(const uint32_t *)(a.mask[i] + o);
+            x[0][i] = xc.x; x[1][i] = xc.y; x[2][i] = xc.z; x[3][i] = xc.w;
+            v[0][i] = vc.x; v[1][i] = vc.y; v[2][i] = vc.z; v[3][i] = vc.w;
+#pragma unroll
+            for (int p = 0; p < CO_PX; ++p) m[p][i] = (uint8_t)(mc >> (8 * p));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int p = 0; p < CO_PX; ++p) {
+                bool in = p < n;
+                x[p][i] = in ? a.cal[i][o + p] : 0.f;
+                v[p][i] = in ? a.var[i][o + p] : 0.f;
+                m[p][i] = in ? a.mask[i][o + p] : (uint8_t)ARGUS_BAD;
+            }
+    }
+    float r[CO_PX], rv[CO_PX];
+    uint8_t rm[CO_PX], nu[CO_PX];
+#pragma unroll
+    for (int p = 0; p < CO_PX; ++p) coadd_one<N>(a, x[p], v[p], m[p], r[p], rv[p], rm[p], nu[p]);
+    if (a.vec && n == CO_PX) {
+        *(float4 *)(a.ref + o) = make_float4(r[0], r[1], r[2], r[3]);
+        *(float4 *)(a.ref_var + o) = make_float4(rv[0], rv[1], rv[2], rv[3]);
+        *(uint32_t *)(a.ref_mask + o) = rm[0] | (rm[1] << 8) | (rm[2] << 16) | ((uint32_t)rm[3] << 24);
+        if (a.n_used)
+            *(uint32_t *)(a.n_used + o) = nu[0] | (nu[1] << 8) | (nu[2] << 16) | ((uint32_t)nu[3] << 24);
+    } else {
+        for (int p = 0; p < n; ++p) {
+            a.ref[o + p] = r[p];
+            a.ref_var[o + p] = rv[p];
+            a.ref_mask[o + p] = rm[p];
+            if (a.n_used) a.n_used[o + p] = nu[p];
+        }
+    }
+}
+
+inline bool aligned(const void *p, size_t al) { return ((uintptr_t)p % al) == 0; }
+
+}  // namespace
+
+int launch_calibrate(argus_ctx *ctx, argus_dims d, const uint16_t *raw, const float *dark,
+                     const float *flat, const uint8_t *bpm, float gain, float rn, uint16_t sat,
+                     float *cal, float *var, uint8_t *mask) {
+    CalArgs a;
+    a.raw = raw; a.dark = dark; a.flat = flat; a.bpm = bpm;
+    a.cal = cal; a.var = var; a.mask = mask;
+    a.pitch = d.pitch; a.W = d.width; a.H = d.height;
+    a.chunks = (d.width + CAL_PX - 1) / CAL_PX;
+    a.inv_g = 1.0 / (double)gain;
+    a.rn2_g2 = (double)rn * (double)rn / ((double)gain * (double)gain);
+    a.sat = (float)sat;
+    a.vec = (d.pitch % CAL_PX == 0) && aligned(raw, 16) && aligned(dark, 16) && aligned(flat, 16) &&
+            (!bpm || aligned(bpm, 8)) && aligned(cal, 16) && (!var || aligned(var, 16)) &&
+            aligned(mask, 8);
+    int64_t total = (int64_t)a.H * a.chunks;
+    dim3 grid((unsigned)((total + 255) / 256));
+    argus_time_begin(ctx);
+    hipLaunchKernelGGL(calibrate_kernel, grid, dim3(256), 0, ctx->stream, a);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, "calibrate");
+    return ARGUS_OK;
+}
+
+int launch_coadd(argus_ctx *ctx, argus_dims d, int n, const float *const *cal,
+                 const float *const *var, const uint8_t *const *mask, float kappa, int max_iter,
+                 float *ref, float *ref_var, uint8_t *ref_mask, uint8_t *n_used) {
+    CoaddArgs a;
+    bool vec = (d.pitch % CO_PX == 0) && aligned(ref, 16) && aligned(ref_var, 16) &&
+               aligned(ref_mask, 4) && (!n_used || aligned(n_used, 4));
+    for (int i = 0; i < ARGUS_MAX_FRAMES; ++i) {
+        a.cal[i] = i < n ? cal[i] : nullptr;
+        a.var[i] = i < n ? var[i] : nullptr;
+        a.mask[i] = i < n ? mask[i] : nullptr;
+        if (i < n) vec = vec && aligned(cal[i], 16) && aligned(var[i], 16) && aligned(mask[i], 4);
+    }
+    a.ref = ref; a.ref_var = ref_var; a.ref_mask = ref_mask; a.n_used = n_used;
+    a.pitch = d.pitch; a.W = d.width; a.H = d.height;
+    a.chunks = (d.width + CO_PX - 1) / CO_PX;
+    a.kappa2 = (double)kappa * (double)kappa;
+    a.max_iter = max_iter;
+    a.vec = vec;
+    int64_t total = (int64_t)a.H * a.chunks;
+    dim3 grid((unsigned)((total + 255) / 256));
+    argus_time_begin(ctx);
+    switch (n) {
+#define ARGUS_CO(N) case N: hipLaunchKernelGGL(coadd_kernel<N>, grid, dim3(256), 0, ctx->stream, a); break;
+        ARGUS_CO(1) ARGUS_CO(2) ARGUS_CO(3) ARGUS_CO(4) ARGUS_CO(5) ARGUS_CO(6) ARGUS_CO(7) ARGUS_CO(8)
+#undef ARGUS_CO
+        default: return argus_fail(ctx, ARGUS_EINVAL, "bad frame count");
+    }
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, "coadd");
+    return ARGUS_OK;
+}

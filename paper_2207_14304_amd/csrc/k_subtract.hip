@@ -1,0 +1,326 @@
+// PSF-matched convolution of the reference, subtraction from the science
+// frame, propagated variance and the fit-set chi^2.
+//
+// Per output pixel p the kernel is evaluated at p (K_p = sum_m P_m(p) K_m).
+// Along a row yt is fixed, so with the stamps ordered (p,q) = (0,0),(0,1),
+// (0,2),(1,0),(1,1),(2,0):  K_p = A0 + xt (A1 + xt A2), A0 = K0 + yt (K1 +
+// yt K2), A1 = K3 + yt K4, A2 = K5.  A thread owns 8 consecutive pixels of a
+// row: the A's of a tap are evaluated once for its row and shared by the 8
+// pixels, the reference and variance windows of a kernel row sit in
+// registers, and each tap costs 5 VALU ops per pixel (2 for a constant
+// kernel).  Workgroups are 128x16 output pixels with an h-pixel halo in LDS.
+#include "internal.h"
+
+namespace {
+
+constexpr int BW = 128, BH = 16, PXT = 8, NTHR = 256;
+
+struct SubArgs {
+    const float *stamps, *bg;
+    const float *ref, *rvar, *sci, *svar;
+    const uint8_t *rmask, *smask;
+    float *diff, *dvar;
+    uint8_t *dmask;
+    double *partials;          // [n_blocks][2]: chi^2, count
+    int64_t pitch;
+    int W, H, D, Dbg;
+    int RX, RY, bpx, bpy;      // regions and blocks per region
+    double sx, sy;
+    int vec;
+};
+
+template <int HH>
+struct SubLds {
+    static constexpr int K = 2 * HH + 1;
+    static constexpr int TH = BH + 2 * HH;
+    static constexpr int TWr = BW + 2 * HH;
+    static constexpr int TW = (TWr + 3) & ~3;          // float row stride, 16-byte aligned
+    static constexpr int MW = (TWr + 15) & ~15;         // mask row stride
+};
+
+template <int D, int HH>
+__global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
+    using L = SubLds<HH>;
+    constexpr int K = L::K, TH = L::TH, TW = L::TW, MW = L::MW, NP = (D + 1) * (D + 2) / 2;
+    constexpr int NS = (D == 0) ? 2 : NP;               // constant kernel also keeps K^2
+    extern __shared__ float lds[];
+    float *Rt = lds;                                    // [TH][TW]
+    float *Vt = Rt + TH * TW;                           // [TH][TW]
+    float *St = Vt + TH * TW;                           // [NS][K*K]
+    uint8_t *Mt = (uint8_t *)(St + NS * K * K);         // [TH][MW] ref mask != 0
+    uint8_t *Mr = Mt + TH * MW;                         // [TH][BW] row-OR over 2h+1
+    __shared__ double red_c[NTHR / 64];
+    __shared__ double red_n[NTHR / 64];
+
+    const int tid = threadIdx.x;
+    const int bid = blockIdx.x;
+    const int bx = bid % a.bpx;
+    const int by = (bid / a.bpx) % a.bpy;
+    const int reg = bid / (a.bpx * a.bpy);
+    const int rx = reg % a.RX, ry = reg / a.RX;
+    const int rx0 = (int)((int64_t)rx * a.W / a.RX), rx1 = (int)((int64_t)(rx + 1) * a.W / a.RX);
+    const int ry0 = (int)((int64_t)ry * a.H / a.RY), ry1 = (int)((int64_t)(ry + 1) * a.H / a.RY);
+    const int bx0 = rx0 + bx * BW, by0 = ry0 + by * BH;
+    const int bx1 = min(bx0 + BW, rx1), by1 = min(by0 + BH, ry1);
+    const int64_t P = a.pitch;
+
+    double c2 = 0.0, cnt = 0.0;
+    if (bx0 < bx1 && by0 < by1) {
+        // halo tiles of the reference, its variance and mask
+        for (int i = tid; i < TH * L::TWr; i += NTHR) {
+            int cy = i / L::TWr, cx = i % L::TWr;
+            int X = bx0 - HH + cx, Y = by0 - HH + cy;
+            bool in = X >= 0 && X < a.W && Y >= 0 && Y < a.H;
+            int64_t o = (int64_t)Y * P + X;
+            Rt[cy * TW + cx] = in ? a.ref[o] : 0.f;
+            Vt[cy * TW + cx] = in ? a.rvar[o] : 0.f;
+            Mt[cy * MW + cx] = in ? (a.rmask[o] != 0) : 0;
+        }
+        const float *src = a.stamps + (size_t)reg * NP * K * K;
+        for (int i = tid; i < NP * K * K; i += NTHR) St[i] = src[i];
+        if (D == 0)
+            for (int i = tid; i < K * K; i += NTHR) { float k = src[i]; St[K * K + i] = k * k; }
+        __syncthreads();
+        for (int i = tid; i < TH * (BW / PXT); i += NTHR) {
+            int cy = i / (BW / PXT), lx0 = (i % (BW / PXT)) * PXT;
+            uint8_t w[PXT + 2 * HH];
+#pragma unroll
+            for (int j = 0; j < PXT + 2 * HH; ++j) w[j] = Mt[cy * MW + lx0 + j];
+#pragma unroll
+            for (int px = 0; px < PXT; ++px) {
+                uint8_t m = 0;
+#pragma unroll
+                for (int uu = 0; uu < K; ++uu) m |= w[px + uu];
+                Mr[cy * BW + lx0 + px] = m;
+            }
+        }
+        __syncthreads();
+
+        const int ly = tid / (BW / PXT), lx0 = (tid % (BW / PXT)) * PXT;
+        const int Y = by0 + ly;
+        float xt[PXT];
+#pragma unroll
+        for (int i = 0; i < PXT; ++i)
+            xt[i] = (float)((double)(bx0 + lx0 + i) * a.sx - (a.sx != 0.0 ? 1.0 : 0.0));
+        const double ytd = (double)Y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
+        const float yt = (float)ytd;
+        float m[PXT], v[PXT];
+#pragma unroll
+        for (int i = 0; i < PXT; ++i) { m[i] = 0.f; v[i] = 0.f; }
+        if (Y < by1) {
+            for (int vv = 0; vv < K; ++vv) {
+                const float *rr = Rt + (ly + 2 * HH - vv) * TW + lx0;
+                const float *qq = Vt + (ly + 2 * HH - vv) * TW + lx0;
+                float r[PXT + 2 * HH], q[PXT + 2 * HH];
+#pragma unroll
+                for (int j = 0; j < PXT + 2 * HH; ++j) { r[j] = rr[j]; q[j] = qq[j]; }
+                const float *st = St + vv * K;
+#pragma unroll
+                for (int uu = 0; uu < K; ++uu) {
+                    if constexpr (D == 0) {
+                        const float k = st[uu], k2 = st[K * K + uu];
+#pragma unroll
+                        for (int i = 0; i < PXT; ++i) {
+                            m[i] += k * r[i + 2 * HH - uu];
+                            v[i] += k2 * q[i + 2 * HH - uu];
+                        }
+                    } else if constexpr (D == 1) {
+                        const float A0 = st[uu] + yt * st[K * K + uu];
+                        const float A1 = st[2 * K * K + uu];
+#pragma unroll
+                        for (int i = 0; i < PXT; ++i) {
+                            const float k = A0 + xt[i] * A1;
+                            m[i] += k * r[i + 2 * HH - uu];
+                            v[i] += (k * k) * q[i + 2 * HH - uu];
+                        }
+                    } else {
+                        const float A0 = st[uu] + yt * (st[K * K + uu] + yt * st[2 * K * K + uu]);
+                        const float A1 = st[3 * K * K + uu] + yt * st[4 * K * K + uu];
+                        const float A2 = st[5 * K * K + uu];
+#pragma unroll
+                        for (int i = 0; i < PXT; ++i) {
+                            const float k = A0 + xt[i] * (A1 + xt[i] * A2);
+                            m[i] += k * r[i + 2 * HH - uu];
+                            v[i] += (k * k) * q[i + 2 * HH - uu];
+                        }
+                    }
+                }
+            }
+            // footprint flags from the row-ORed mask
+            uint8_t foot[PXT];
+#pragma unroll
+            for (int i = 0; i < PXT; ++i) foot[i] = 0;
+            for (int vv = 0; vv < K; ++vv) {
+#pragma unroll
+                for (int i = 0; i < PXT; ++i) foot[i] |= Mr[(ly + vv) * BW + lx0 + i];
+            }
+            // background polynomial of this pixel's solve
+            const float *bgp = a.bg + (size_t)reg * ((a.Dbg + 1) * (a.Dbg + 2) / 2);
+            float outd[PXT], outv[PXT];
+            uint8_t outm[PXT];
+            const int64_t orow = (int64_t)Y * P;
+#pragma unroll
+            for (int i = 0; i < PXT; ++i) {
+                const int X = bx0 + lx0 + i;
+                outd[i] = 0.f; outv[i] = 0.f; outm[i] = 0;
+                if (X < bx1) {
+                    const int64_t o = orow + X;
+                    const bool edge = X < HH || X > a.W - 1 - HH || Y < HH || Y > a.H - 1 - HH;
+                    uint8_t dm = a.smask[o] | (edge ? ARGUS_EDGE : 0u) |
+                                 ((!edge && foot[i]) ? ARGUS_FOOT : 0u);
+                    outm[i] = dm;
+                    if (dm == 0) {
+                        double xd = (double)X * a.sx - (a.sx != 0.0 ? 1.0 : 0.0);
+                        double bgv = 0.0;
+                        int mi = 0;
+                        for (int pp = 0; pp <= a.Dbg; ++pp) {
+                            double xp = 1.0;
+                            for (int e = 0; e < pp; ++e) xp *= xd;
+                            double yq = 1.0;
+                            for (int qq2 = 0; qq2 <= a.Dbg - pp; ++qq2, ++mi) {
+                                bgv += (double)bgp[mi] * xp * yq;
+                                yq *= ytd;
+                            }
+                        }
+                        const float s = a.sci[o], sv = a.svar[o];
+                        const float dval = s - (float)((double)m[i] + bgv);
+                        outd[i] = dval;
+                        outv[i] = sv + v[i];
+                        const float tot = sv + a.rvar[o];
+                        if (tot > 0.f) {
+                            c2 += (double)dval * (double)dval / (double)tot;
+                            cnt += 1.0;
+                        }
+                    }
+                }
+            }
+            const int X0 = bx0 + lx0;
+            const int64_t o0 = orow + X0;
+            if (a.vec && (X0 & 7) == 0 && X0 + PXT <= bx1) {
+                *(float4 *)(a.diff + o0) = make_float4(outd[0], outd[1], outd[2], outd[3]);
+                *(float4 *)(a.diff + o0 + 4) = make_float4(outd[4], outd[5], outd[6], outd[7]);
+                *(float4 *)(a.dvar + o0) = make_float4(outv[0], outv[1], outv[2], outv[3]);
+                *(float4 *)(a.dvar + o0 + 4) = make_float4(outv[4], outv[5], outv[6], outv[7]);
+                uint2 mo;
+                mo.x = outm[0] | (outm[1] << 8) | (outm[2] << 16) | ((uint32_t)outm[3] << 24);
+                mo.y = outm[4] | (outm[5] << 8) | (outm[6] << 16) | ((uint32_t)outm[7] << 24);
+                *(uint2 *)(a.dmask + o0) = mo;
+            } else {
+#pragma unroll
+                for (int i = 0; i < PXT; ++i) {
+                    if (X0 + i < bx1) {
+                        a.diff[o0 + i] = outd[i];
+                        a.dvar[o0 + i] = outv[i];
+                        a.dmask[o0 + i] = outm[i];
+                    }
+                }
+            }
+        }
+    }
+    // fixed-order block reduction of chi^2 and the fit-set count
+    for (int off = 32; off > 0; off >>= 1) {
+        c2 += __shfl_xor(c2, off);
+        cnt += __shfl_xor(cnt, off);
+    }
+    if ((tid & 63) == 0) { red_c[tid >> 6] = c2; red_n[tid >> 6] = cnt; }
+    __syncthreads();
+    if (tid == 0) {
+        double sc = 0.0, sn = 0.0;
+        for (int i = 0; i < NTHR / 64; ++i) { sc += red_c[i]; sn += red_n[i]; }
+        a.partials[2 * (size_t)bid] = sc;
+        a.partials[2 * (size_t)bid + 1] = sn;
+    }
+}
+
+// One workgroup per solve: fixed-order sum of its blocks' partials.
+__global__ void chi2_reduce_kernel(const double *part, int per_solve, double *chi2, int64_t *n) {
+    __shared__ double rc[4], rn[4];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    double c = 0.0, k = 0.0;
+    for (int j = tid; j < per_solve; j += blockDim.x) {
+        c += part[2 * ((size_t)s * per_solve + j)];
+        k += part[2 * ((size_t)s * per_solve + j) + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off);
+        k += __shfl_xor(k, off);
+    }
+    if ((tid & 63) == 0) { rc[tid >> 6] = c; rn[tid >> 6] = k; }
+    __syncthreads();
+    if (tid == 0) {
+        double sc = 0.0, sn = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { sc += rc[i]; sn += rn[i]; }
+        if (chi2) chi2[s] = sc;
+        if (n) n[s] = (int64_t)sn;
+    }
+}
+
+template <int D, int HH>
+int sub_launch(argus_ctx *ctx, SubArgs &a, int n_blocks) {
+    using L = SubLds<HH>;
+    constexpr int NP = (D + 1) * (D + 2) / 2;
+    constexpr int NS = (D == 0) ? 2 : NP;
+    size_t lds = (size_t)2 * L::TH * L::TW * 4 + (size_t)NS * L::K * L::K * 4 +
+                 (size_t)L::TH * L::MW + (size_t)L::TH * BW;
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)subtract_kernel<D, HH>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((subtract_kernel<D, HH>), dim3(n_blocks), dim3(NTHR), lds, ctx->stream, a);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    return ARGUS_OK;
+}
+
+template <int D>
+int sub_dispatch_h(argus_ctx *ctx, SubArgs &a, int h, int n_blocks) {
+    switch (h) {
+#define ARGUS_SH(HH) case HH: return sub_launch<D, HH>(ctx, a, n_blocks);
+        ARGUS_SH(1) ARGUS_SH(2) ARGUS_SH(3) ARGUS_SH(4) ARGUS_SH(5) ARGUS_SH(6) ARGUS_SH(7)
+        ARGUS_SH(8) ARGUS_SH(9) ARGUS_SH(10) ARGUS_SH(11) ARGUS_SH(12) ARGUS_SH(13)
+        ARGUS_SH(14) ARGUS_SH(15)
+#undef ARGUS_SH
+        default: return argus_fail(ctx, ARGUS_ESHAPE, "half width %d unsupported", h);
+    }
+}
+
+inline bool aligned(const void *p, size_t al) { return ((uintptr_t)p % al) == 0; }
+
+}  // namespace
+
+int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
+                    const float *stamps, const float *bg, const float *ref,
+                    const float *ref_var, const uint8_t *ref_mask, const float *sci,
+                    const float *sci_var, const uint8_t *sci_mask, float *diff, float *diff_var,
+                    uint8_t *diff_mask, double *chi2, int64_t *n_chi2) {
+    SubArgs a;
+    a.stamps = stamps; a.bg = bg; a.ref = ref; a.rvar = ref_var; a.sci = sci; a.svar = sci_var;
+    a.rmask = ref_mask; a.smask = sci_mask; a.diff = diff; a.dvar = diff_var; a.dmask = diff_mask;
+    a.pitch = d.pitch; a.W = d.width; a.H = d.height;
+    a.D = spec->spatial_degree; a.Dbg = spec->bg_degree;
+    const bool global = spec->mode == ARGUS_FIT_GLOBAL;
+    a.RX = global ? 1 : spec->tiles_x;
+    a.RY = global ? 1 : spec->tiles_y;
+    a.bpx = ((d.width + a.RX - 1) / a.RX + BW - 1) / BW;
+    a.bpy = ((d.height + a.RY - 1) / a.RY + BH - 1) / BH;
+    a.sx = d.width > 1 ? 2.0 / (d.width - 1) : 0.0;
+    a.sy = d.height > 1 ? 2.0 / (d.height - 1) : 0.0;
+    a.vec = (d.pitch % 8 == 0) && aligned(diff, 32) && aligned(diff_var, 32) && aligned(diff_mask, 8);
+    const int n_solves = a.RX * a.RY;
+    const int per_solve = a.bpx * a.bpy;
+    const int n_blocks = n_solves * per_solve;
+    int rc = argus_ws_reserve(ctx, (size_t)n_blocks * 2 * sizeof(double) + 256);
+    if (rc) return rc;
+    a.partials = (double *)ctx->ws;
+    argus_time_begin(ctx);
+    switch (a.D) {
+        case 0: rc = sub_dispatch_h<0>(ctx, a, spec->half_width, n_blocks); break;
+        case 1: rc = sub_dispatch_h<1>(ctx, a, spec->half_width, n_blocks); break;
+        default: rc = sub_dispatch_h<2>(ctx, a, spec->half_width, n_blocks); break;
+    }
+    if (rc) return rc;
+    argus_time_end(ctx, "subtract");
+    if (chi2 || n_chi2) {
+        hipLaunchKernelGGL(chi2_reduce_kernel, dim3(n_solves), dim3(256), 0, ctx->stream,
+                           (const double *)a.partials, per_solve, chi2, n_chi2);
+        ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    }
+    return ARGUS_OK;
+}
