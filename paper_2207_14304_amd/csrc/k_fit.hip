@@ -152,7 +152,9 @@ struct WaveGram {
                 for (int r = 0; r < 4; ++r) F[j][b][r] = 0.0;
     }
 
-    __device__ void row(const float *cvec, const float *wx, const double *ypw, int lane) {
+    // c'_k = c_k + gam_k c_0 is applied to the operands as they are loaded.
+    __device__ void row(const float *cvec, const float *wx, const double *ypw, int lane,
+                        float g0, float g1) {
         if constexpr (NTW > 0) {
             floatx4 acc[NTW];
 #pragma unroll
@@ -161,8 +163,9 @@ struct WaveGram {
 #pragma unroll 4
             for (int s = 0; s < SW / 4; ++s) {
                 const int p = 4 * s + pk;
-                const float c0 = cvec[p * CST + col];
-                const float c1 = cvec[p * CST + 16 + col];
+                const float cz = cvec[p * CST];
+                const float c0 = cvec[p * CST + col] + g0 * cz;
+                const float c1 = cvec[p * CST + 16 + col] + g1 * cz;
 #pragma unroll
                 for (int j = 0; j < NTW; ++j) {
                     const int t = WAVE + 4 * j;
@@ -207,46 +210,52 @@ struct WaveGram {
     }
 };
 
-// LDS carve-up of the accumulation kernel (offsets in 4-byte words, then bytes).
-template <int D>
+// Wave-uniform loads of the filter tables go through the scalar cache.
+typedef const __attribute__((address_space(4))) float *cfloat_p;
+__device__ __forceinline__ float uload(const float *p) { return *(cfloat_p)p; }
+
+// LDS carve-up of the accumulation kernel (4-byte words).
+template <int D, int HH>
 struct FitLds {
-    float *rowf, *colf, *gam, *rowbuf, *inrow, *cvec, *wx, *wsx, *xtp;
-    int *kinfo;
-    uint8_t *mbuf, *minrow;
-    __host__ __device__ static size_t words(int nplanes, int K) {
+    static constexpr int K = 2 * HH + 1;
+    static constexpr int IN = SW + 2 * HH;               // input row length
+    static constexpr int INP = (IN + 3) & ~3;
+    float *rowbuf, *inrow, *cvec, *wx, *wsx;
+    uint8_t *minrow;
+    __host__ __device__ static size_t bytes(int nplanes) {
         using S = FitShape<D>;
-        return ARGUS_MAX_PLANES * 32 + 32 * 32 + 32 + (size_t)nplanes * K * SW + SW + 32 +
-               SW * CST + (S::NA + S::NRA) * SW + SW + 32;
+        size_t w = (size_t)nplanes * K * SW + 2 * INP + SW * CST + (S::NA + S::NRA) * SW;
+        size_t b = w * 4 + 2 * INP;
+        size_t rhs = (size_t)8 * S::NR * 32 * 8 + 256;    // end-of-kernel reuse of rowbuf
+        return (b > rhs ? b : rhs) + 64;
     }
-    __device__ FitLds(float *lds, int nplanes, int K) {
+    __device__ FitLds(float *lds, int nplanes) {
         using S = FitShape<D>;
-        rowf = lds;                                     // [16][32]
-        colf = rowf + ARGUS_MAX_PLANES * 32;            // [32][32]
-        gam = colf + 32 * 32;                           // [32]
-        rowbuf = gam + 32;                              // [NPL][K][SW] circular rows
-        inrow = rowbuf + (size_t)nplanes * K * SW;      // [SW + 2h], padded to SW + 32
-        cvec = inrow + SW + 32;                         // [SW][CST]
-        wx = cvec + SW * CST;                           // [NA][SW]
-        wsx = wx + S::NA * SW;                          // [NRA][SW]
-        xtp = wsx + S::NRA * SW;                        // [SW]
-        kinfo = (int *)(xtp + SW);                      // [16] first k, [16] count
-        mbuf = (uint8_t *)(kinfo + 32);                 // [K][SW]
-        minrow = mbuf + (size_t)K * SW;                 // [SW + 32]
+        rowbuf = lds;                                   // [NPL][K][SW]: thread-private columns
+        inrow = rowbuf + (size_t)nplanes * K * SW;      // [2][INP] double-buffered input row
+        cvec = inrow + 2 * INP;                         // [SW][CST] raw basis convolutions
+        wx = cvec + SW * CST;                           // [NA][SW]  w xt^a
+        wsx = wx + S::NA * SW;                          // [NRA][SW] w S xt^a
+        minrow = (uint8_t *)(wsx + S::NRA * SW);        // [2][INP] ref mask != 0
     }
 };
 
-template <int D, int WAVE>
+// One workgroup: a 64-column strip of a region, rows [ry0, ry1).  Wave w owns
+// the row-filter planes w, w+4, w+8, w+12 at column x = lane (its slice of the
+// circular row buffer is private, so the row and column passes need no
+// barrier between them); wave 0 also owns the fit-set weights.  Per input row:
+// write the prefetched row to LDS, prefetch the next one, barrier, row filters,
+// column filters + weights, barrier, MFMA moments and rhs of the output row.
+template <int D, int HH, int WAVE>
 __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0, int ry1,
                          bool active, double *part) {
     using S = FitShape<D>;
+    using L = FitLds<D, HH>;
+    constexpr int K = L::K;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int h = a.h, K = 2 * h + 1, NPL = a.nplanes, nb = a.nb;
-    FitLds<D> L(lds, NPL, K);
-    float *rowf = L.rowf, *colf = L.colf, *gam = L.gam, *rowbuf = L.rowbuf, *inrow = L.inrow;
-    float *cvec = L.cvec, *wx = L.wx, *wsx = L.wsx, *xtp = L.xtp;
-    int *kinfo = L.kinfo;
-    uint8_t *mbuf = L.mbuf, *minrow = L.minrow;
-    double *rhsbuf = (double *)rowbuf;                  // reused at the end
+    const int NPL = a.nplanes;
+    L l(lds, NPL);
+    double *rhsbuf = (double *)lds;
 
     WaveGram<D, WAVE> gram;
     gram.zero();
@@ -255,120 +264,179 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
     for (int i = 0; i < S::NR; ++i) RF[i] = 0.0;
     int count = 0;
 
+    // per-plane constants of this wave (wave-uniform)
+    int k0[4], nk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = WAVE + 4 * j;
+        k0[j] = 0;
+        nk[j] = 0;
+        if (p < NPL) {
+            for (int k = 0; k < a.nb; ++k)
+                if (a.tab->kpl[k] == p) {
+                    if (nk[j] == 0) k0[j] = k;
+                    ++nk[j];
+                }
+        }
+        k0[j] = __builtin_amdgcn_readfirstlane(k0[j]);
+        nk[j] = __builtin_amdgcn_readfirstlane(nk[j]);
+    }
+    const float g0 = (lane & 15) < a.nb ? a.tab->gam[lane & 15] : 0.f;
+    const float g1 = 16 + (lane & 15) < a.nb ? a.tab->gam[16 + (lane & 15)] : 0.f;
+    const float gk = (lane & 31) < a.nb ? a.tab->gam[lane & 31] : 0.f;  // rhs fix-up
+    const float xt = (float)((double)(sx0 + lane) * a.sx - (a.sx != 0.0 ? 1.0 : 0.0));
+
     const int64_t P = a.pitch;
-    const int yend = active ? ry1 + h : ry0 - h;
-    for (int yy = ry0 - h; yy < yend; ++yy) {
-        // P1: input row yy, columns sx0-h .. sx0+SW+h-1 (0 outside the image)
-        for (int j = tid; j < SW + 2 * h; j += NTHR) {
-            int X = sx0 - h + j;
+    // prefetch registers: input row element (threads < IN) and the weight inputs
+    float pr = 0.f;
+    uint8_t pm = 0;
+    float p_s = 0.f, p_sv = 0.f, p_rv = 0.f;
+    uint8_t p_sm = 1;
+    auto fetch_in = [&](int yy) {
+        if (tid < L::IN) {
+            int X = sx0 - HH + tid;
             bool in = X >= 0 && X < a.W;
-            inrow[j] = in ? a.ref[(int64_t)yy * P + X] : 0.f;
-            minrow[j] = in ? (a.rmask[(int64_t)yy * P + X] != 0) : 0;
+            pr = in ? a.ref[(int64_t)yy * P + X] : 0.f;
+            pm = in ? (a.rmask[(int64_t)yy * P + X] != 0) : 0;
         }
+    };
+    auto fetch_w = [&](int y) {
+        if (WAVE == 0 && y >= ry0 && y < ry1 && sx0 + lane < sx1) {
+            int64_t o = (int64_t)y * P + sx0 + lane;
+            p_s = a.sci[o];
+            p_sv = a.svar[o];
+            p_rv = a.rvar[o];
+            p_sm = a.smask[o];
+        } else {
+            p_sm = 1;
+        }
+    };
+    uint32_t hist = 0;                     // bit j: input row yy-j has a flagged pixel in reach
+    const int yend = active ? ry1 + HH : ry0 - HH;
+    if (active) {
+        fetch_in(ry0 - HH);
+        fetch_w(ry0);
+    }
+    for (int yy = ry0 - HH; yy < yend; ++yy) {
+        const int buf = yy & 1;
+        if (tid < L::IN) {
+            l.inrow[buf * L::INP + tid] = pr;
+            l.minrow[buf * L::INP + tid] = pm;
+        }
+        const float w_s = p_s, w_sv = p_sv, w_rv = p_rv;
+        const uint8_t w_sm = p_sm;
+        if (yy + 1 < yend) fetch_in(yy + 1);
+        const bool outrow = yy >= ry0 + HH;
+        if (outrow) fetch_w(yy + 1 - HH);
         __syncthreads();
-        // P2: row filters for every plane; row-OR of the reference mask
+        // row filters of my planes at x = lane
         const int slot = yy % K;
-        for (int it = tid; it < NPL * SW; it += NTHR) {
-            int p = it / SW, x = it % SW;
-            const float *f = rowf + p * 32;
-            float acc = 0.f;
-            for (int uu = 0; uu < K; ++uu) acc += f[uu] * inrow[x + 2 * h - uu];
-            rowbuf[(p * K + slot) * SW + x] = acc;
-        }
-        if (tid < SW) {
-            uint8_t m = 0;
-            for (int uu = 0; uu < K; ++uu) m |= minrow[tid + uu];
-            mbuf[slot * SW + tid] = m;
-        }
-        __syncthreads();
-        if (yy < ry0 + h) continue;
-        const int y = yy - h;
-        // P3: column filters -> raw separable convolutions in cvec
-        for (int it = tid; it < NPL * SW; it += NTHR) {
-            int p = it / SW, x = it % SW;
-            int k0 = kinfo[p], nk = kinfo[16 + p];
-            float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int vv = 0; vv < K; ++vv) {
-                int row = y + h - vv;
-                float t = rowbuf[(p * K + row % K) * SW + x];
+        {
+            float win[K];
+            const float *ir = l.inrow + buf * L::INP + lane;
 #pragma unroll
-                for (int q = 0; q < 5; ++q)
-                    if (q < nk) acc[q] += colf[(k0 + q) * 32 + vv] * t;
+            for (int uu = 0; uu < K; ++uu) win[uu] = ir[2 * HH - uu];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = WAVE + 4 * j;
+                if (p < NPL) {
+                    const float *f = &a.tab->rowf[p][0];
+                    float acc = 0.f;
+#pragma unroll
+                    for (int uu = 0; uu < K; ++uu) acc += uload(f + uu) * win[uu];
+                    l.rowbuf[((size_t)p * K + slot) * SW + lane] = acc;
+                }
             }
+            if (WAVE == 0) {
+                const uint8_t *mr = l.minrow + buf * L::INP + lane;
+                uint8_t m = 0;
 #pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (q < nk) cvec[x * CST + k0 + q] = acc[q];
+                for (int uu = 0; uu < K; ++uu) m |= mr[uu];
+                hist = (hist << 1) | (m ? 1u : 0u);
+            }
         }
-        // fit-set weights of this output row
-        if (tid < SW) {
-            const int X = sx0 + tid;
-            float w = 0.f, Sv = 0.f;
-            if (X < sx1) {
-                uint8_t foot = 0;
-                for (int q = 0; q < K; ++q) foot |= mbuf[q * SW + tid];
-                int64_t o = (int64_t)y * P + X;
-                float sv = a.svar[o], rv = a.rvar[o];
-                Sv = a.sci[o];
-                float tot = sv + rv;
-                if (a.smask[o] == 0 && foot == 0 && tot > 0.f) {
+        if (outrow) {
+            const int y = yy - HH;
+            // column filters: rows y-h..y+h sit in slots (yy+1 .. yy+K) mod K
+            int s0 = (yy + 1) % K;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = WAVE + 4 * j;
+                if (p < NPL) {
+                    float t[K];
+#pragma unroll
+                    for (int jj = 0; jj < K; ++jj) {
+                        int sl = s0 + jj;
+                        sl -= sl >= K ? K : 0;
+                        t[jj] = l.rowbuf[((size_t)p * K + sl) * SW + lane];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        if (q < nk[j]) {
+                            const float *f = &a.tab->colf[k0[j] + q][0];
+                            float acc = 0.f;
+#pragma unroll
+                            for (int jj = 0; jj < K; ++jj) acc += uload(f + 2 * HH - jj) * t[jj];
+                            l.cvec[lane * CST + k0[j] + q] = acc;
+                        }
+                    }
+                }
+            }
+            if (WAVE == 0) {
+                const bool foot = (hist & ((1u << K) - 1u)) != 0;
+                const float tot = w_sv + w_rv;
+                float w = 0.f;
+                if (w_sm == 0 && !foot && tot > 0.f) {
                     w = 1.0f / tot;
                     ++count;
                 }
-            }
-            float xt = xtp[tid], xp = 1.f;
+                float xp = 1.f;
 #pragma unroll
-            for (int e = 0; e < S::NA; ++e) {
-                wx[e * SW + tid] = w * xp;
-                if (e < S::NRA) wsx[e * SW + tid] = w * Sv * xp;
-                xp *= xt;
+                for (int e = 0; e < S::NA; ++e) {
+                    l.wx[e * SW + lane] = w * xp;
+                    if (e < S::NRA) l.wsx[e * SW + lane] = w * w_s * xp;
+                    xp *= xt;
+                }
             }
         }
         __syncthreads();
-        // P4: flux-normalised combination C'_k += gam_k C'_0
-        for (int it = tid; it < SW * nb; it += NTHR) {
-            int x = it / nb, k = it % nb;
-            float g = gam[k];
-            if (k > 0 && g != 0.f) cvec[x * CST + k] += g * cvec[x * CST];
-        }
-        __syncthreads();
-        // P5: MFMA Gram moments of this row and VALU right-hand side
-        double ypw[2 * D + 1];
-        {
-            double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
-            double yp = 1.0;
+        if (outrow) {
+            const int y = yy - HH;
+            double ypw[2 * D + 1];
+            {
+                double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
+                double yp = 1.0;
 #pragma unroll
-            for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
-        }
-        gram.row(cvec, wx, ypw, lane);
-        {
-            const int k = lane & 31, half = lane >> 5;
-            float ra[S::NRA];
-#pragma unroll
-            for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int px = WAVE * 16 + half * 8 + i;
-                const float c = cvec[px * CST + k];
-#pragma unroll
-                for (int e = 0; e < S::NRA; ++e) ra[e] += wsx[e * SW + px] * c;
+                for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
             }
+            gram.row(l.cvec, l.wx, ypw, lane, g0, g1);
+            {
+                const int k = lane & 31, half = lane >> 5;
+                float ra[S::NRA];
 #pragma unroll
-            for (int e = 0; e < S::NRA; ++e)
+                for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
 #pragma unroll
-                for (int b = 0; b <= D; ++b)
-                    if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
+                for (int i = 0; i < 8; ++i) {
+                    const int px = WAVE * 16 + half * 8 + i;
+                    const float c = l.cvec[px * CST + k] + gk * l.cvec[px * CST];
+#pragma unroll
+                    for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsx[e * SW + px] * c;
+                }
+#pragma unroll
+                for (int e = 0; e < S::NRA; ++e)
+#pragma unroll
+                    for (int b = 0; b <= D; ++b)
+                        if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
+            }
         }
     }
     __syncthreads();
-    // Gram partials: every (moment, block pair) element is written by one lane
     gram.store(part, lane);
-    // rhs: 8 half-wave partials per (moment, k), summed in a fixed order
     {
         const int k = lane & 31, half = lane >> 5;
 #pragma unroll
         for (int i = 0; i < S::NR; ++i) rhsbuf[((WAVE * 2 + half) * S::NR + i) * 32 + k] = RF[i];
     }
-    // fit-pixel count (wave 0 holds it)
     if (WAVE == 0) {
         double c = (double)count;
         for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
@@ -382,7 +450,7 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
     }
 }
 
-template <int D>
+template <int D, int HH>
 __global__ __launch_bounds__(NTHR) void fit_accum_kernel(FitArgs a) {
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
@@ -391,8 +459,8 @@ __global__ __launch_bounds__(NTHR) void fit_accum_kernel(FitArgs a) {
     const int rc = blockIdx.y % a.rchunks, ry = blockIdx.y / a.rchunks;
     const int rx0 = (int)((int64_t)rx * a.W / a.RX), rx1 = (int)((int64_t)(rx + 1) * a.W / a.RX);
     const int ry0g = (int)((int64_t)ry * a.H / a.RY), ry1g = (int)((int64_t)(ry + 1) * a.H / a.RY);
-    const int ix0 = max(rx0, a.h), ix1 = min(rx1, a.W - a.h);
-    const int iy0 = max(ry0g, a.h), iy1 = min(ry1g, a.H - a.h);
+    const int ix0 = max(rx0, HH), ix1 = min(rx1, a.W - HH);
+    const int iy0 = max(ry0g, HH), iy1 = min(ry1g, a.H - HH);
     int sx0 = ix0 + s * SW, sx1 = min(sx0 + SW, ix1);
     int rows = max(iy1 - iy0, 0);
     int rh = (rows + a.rchunks - 1) / a.rchunks;
@@ -400,38 +468,17 @@ __global__ __launch_bounds__(NTHR) void fit_accum_kernel(FitArgs a) {
     const bool active = sx0 < sx1 && ry0 < ry1;    // otherwise the partial is all zeros
     const int pid = ((ry * a.RX + rx) * a.rchunks + rc) * a.spt + s;
     double *part = a.partials + (size_t)pid * a.stride;
-
-    // stage the filter tables and per-strip constants
-    const int K = 2 * a.h + 1;
-    FitLds<D> L(lds, a.nplanes, K);
-    float *rowf = L.rowf, *colf = L.colf, *gam = L.gam, *xtp = L.xtp, *cvec = L.cvec;
-    int *kinfo = L.kinfo;
-    for (int i = tid; i < ARGUS_MAX_PLANES * 32; i += NTHR) rowf[i] = (&a.tab->rowf[0][0])[i];
-    for (int i = tid; i < 32 * 32; i += NTHR) colf[i] = (&a.tab->colf[0][0])[i];
-    if (tid < 32) gam[tid] = tid < a.nb ? a.tab->gam[tid] : 0.f;
-    if (tid < SW) {
-        int X = sx0 + tid;
-        xtp[tid] = (float)((double)X * a.sx - (a.sx != 0.0 ? 1.0 : 0.0));
-    }
-    if (tid == 0) {
-        for (int p = 0; p < 16; ++p) { kinfo[p] = 0; kinfo[16 + p] = 0; }
-        for (int k = 0; k < a.nb; ++k) {
-            int p = a.tab->kpl[k];
-            if (kinfo[16 + p] == 0) kinfo[p] = k;
-            kinfo[16 + p]++;
-        }
-    }
     // constant tail of c: 1 at index nb (background), zeros after
+    FitLds<D, HH> L(lds, a.nplanes);
     for (int i = tid; i < SW * CST; i += NTHR) {
         int k = i % CST;
-        cvec[i] = (k == a.nb) ? 1.f : 0.f;
+        if (k >= a.nb) L.cvec[i] = (k == a.nb) ? 1.f : 0.f;
     }
-    __syncthreads();
     switch (tid >> 6) {
-        case 0: fit_wave<D, 0>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 1: fit_wave<D, 1>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 2: fit_wave<D, 2>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        default: fit_wave<D, 3>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        case 0: fit_wave<D, HH, 0>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        case 1: fit_wave<D, HH, 1>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        case 2: fit_wave<D, HH, 2>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
+        default: fit_wave<D, HH, 3>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
     }
 }
 
@@ -572,16 +619,11 @@ __global__ __launch_bounds__(NTHR) void fit_solve_kernel(SolveArgs a) {
         for (int i = j + 1 + tid; i < n; i += NTHR) L[i * (i + 1) / 2 + j] /= ljj;
         if (tid == 0) L[j * (j + 1) / 2 + j] = ljj;
         __syncthreads();
-        // trailing update of rows i > j, columns j < c <= i
-        const int m = n - j - 1;
-        const int nupd = m * (m + 1) / 2;
-        for (int idx = tid; idx < nupd; idx += NTHR) {
-            int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-            while ((r + 1) * (r + 2) / 2 <= idx) ++r;
-            while (r * (r + 1) / 2 > idx) --r;
-            int c = idx - r * (r + 1) / 2;
-            int i = j + 1 + r, cc = j + 1 + c;
-            L[i * (i + 1) / 2 + cc] -= L[i * (i + 1) / 2 + j] * L[cc * (cc + 1) / 2 + j];
+        // trailing update of rows i > j, columns j < c <= i (16 x 16 thread grid)
+        for (int i = j + 1 + (tid & 15); i < n; i += 16) {
+            const double lij = L[i * (i + 1) / 2 + j];
+            double *Li = L + i * (i + 1) / 2;
+            for (int c = j + 1 + (tid >> 4); c <= i; c += 16) Li[c] -= lij * L[c * (c + 1) / 2 + j];
         }
         __syncthreads();
     }
@@ -631,17 +673,6 @@ __global__ void expand_kernel(const BasisTables *T, const double *coeffs, int n,
 }
 
 template <int D>
-size_t fit_lds_bytes(int h, int nplanes) {
-    using S = FitShape<D>;
-    int K = 2 * h + 1;
-    size_t bytes = FitLds<D>::words(nplanes, K) * 4 + (size_t)K * SW + SW + 32;
-    size_t rhs = (size_t)8 * S::NR * 32 * 8;          // reuses rowbuf at the end
-    size_t rowbuf_bytes = (size_t)nplanes * K * SW * 4;
-    if (rhs > rowbuf_bytes) bytes += rhs - rowbuf_bytes;
-    return (bytes + 15) & ~(size_t)15;
-}
-
-template <int D>
 int fit_launch_d(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, FitArgs &fa,
                  int n_regions, int parts_per_region, double **sums_out) {
     using S = FitShape<D>;
@@ -659,12 +690,24 @@ int fit_launch_d(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, Fi
     fa.partials = base;
     double *stage1 = base + (size_t)n_parts * fa.stride;
     double *sums = stage1 + (size_t)n_g1 * fa.stride;
-    size_t lds = fit_lds_bytes<D>(fa.h, fa.nplanes);
-    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)fit_accum_kernel<D>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     dim3 grid(fa.RX * fa.spt, fa.RY * fa.rchunks);
     argus_time_begin(ctx);
-    hipLaunchKernelGGL(fit_accum_kernel<D>, grid, dim3(NTHR), lds, ctx->stream, fa);
+    switch (fa.h) {
+#define ARGUS_FH(HH)                                                                        \
+    case HH: {                                                                              \
+        size_t lds = FitLds<D, HH>::bytes(fa.nplanes);                                      \
+        ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)fit_accum_kernel<D, HH>,     \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                                 (int)lds));                                \
+        hipLaunchKernelGGL((fit_accum_kernel<D, HH>), grid, dim3(NTHR), lds, ctx->stream, fa); \
+        break;                                                                              \
+    }
+        ARGUS_FH(1) ARGUS_FH(2) ARGUS_FH(3) ARGUS_FH(4) ARGUS_FH(5) ARGUS_FH(6) ARGUS_FH(7)
+        ARGUS_FH(8) ARGUS_FH(9) ARGUS_FH(10) ARGUS_FH(11) ARGUS_FH(12) ARGUS_FH(13)
+        ARGUS_FH(14) ARGUS_FH(15)
+#undef ARGUS_FH
+        default: return argus_fail(ctx, ARGUS_ESHAPE, "half width %d unsupported", fa.h);
+    }
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     argus_time_end(ctx, "fit_accum");
     argus_time_begin(ctx);
