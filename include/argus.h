@@ -66,8 +66,9 @@ extern "C" {
 /* ---- fit modes and precisions ------------------------------------------ */
 #define ARGUS_FIT_GLOBAL   0  /* one solve; tiles only order the partial sums */
 #define ARGUS_FIT_PER_TILE 1  /* one independent solve per tile              */
-#define ARGUS_FP32   0        /* normal equations on FP32 MFMA               */
+#define ARGUS_FP32   0        /* row moments on FP32 MFMA, FP64 row sums     */
 #define ARGUS_BF16X3 1        /* hi/lo-split BF16 MFMA, FP32 accumulation    */
+#define ARGUS_FP64   2        /* row moments on FP64 MFMA                    */
 
 typedef struct argus_ctx argus_ctx;
 
@@ -94,7 +95,7 @@ typedef struct {
     int32_t bg_degree;        /* 0..spatial_degree */
     int32_t tiles_x, tiles_y; /* >= 1 */
     int32_t mode;             /* ARGUS_FIT_GLOBAL or ARGUS_FIT_PER_TILE */
-    int32_t precision;        /* ARGUS_FP32 or ARGUS_BF16X3 */
+    int32_t precision;        /* ARGUS_FP32, ARGUS_BF16X3 or ARGUS_FP64 */
 } argus_kernel_spec;
 
 typedef struct {

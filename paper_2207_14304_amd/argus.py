@@ -19,7 +19,7 @@ OK, EINVAL, ESHAPE, ENOMEM, EHIP, EBUSY = 0, -1, -2, -3, -4, -5
 ESINGULAR, ETOOFEW = -20, -21
 BAD, SAT, EDGE, NODATA, FOOT, DET, CAND = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20, 0x40
 FIT_GLOBAL, FIT_PER_TILE = 0, 1
-FP32, BF16X3 = 0, 1
+FP32, BF16X3, FP64 = 0, 1, 2
 
 # every symbol declared in include/argus.h
 SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "argus_last_error",

@@ -181,7 +181,7 @@ static int check_spec(argus_ctx *ctx, const argus_kernel_spec *s) {
         return argus_fail(ctx, ARGUS_ESHAPE, "tiles must be 1..4096 per axis");
     if (s->mode != ARGUS_FIT_GLOBAL && s->mode != ARGUS_FIT_PER_TILE)
         return argus_fail(ctx, ARGUS_EINVAL, "bad fit mode %d", s->mode);
-    if (s->precision != ARGUS_FP32 && s->precision != ARGUS_BF16X3)
+    if (s->precision != ARGUS_FP32 && s->precision != ARGUS_BF16X3 && s->precision != ARGUS_FP64)
         return argus_fail(ctx, ARGUS_EINVAL, "bad precision %d", s->precision);
     return ARGUS_OK;
 }

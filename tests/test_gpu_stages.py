@@ -184,7 +184,8 @@ def test_subtract_delta_identity(ctx):
 # Noise-free, in-span data: the fit must return the generating kernel.  FP32
 # moment products and 64-pixel FP32 row sums bound the stamp error near 1e-3 on
 # these sparse fields (a numpy emulation of the same arithmetic gives 1.2e-3).
-EXACT_STAMP_TOL = {argus.FP32: 2e-3}
+# FP64 MFMA removes that floor; the BF16x3 split keeps ~16 bits per product.
+EXACT_STAMP_TOL = {argus.FP32: 2e-3, argus.FP64: 2e-5, argus.BF16X3: 0.5}
 
 
 def _fit(ctx, spec, planes):
@@ -204,13 +205,14 @@ def _fit(ctx, spec, planes):
     return host(co), host(nf), host(st), host(stamps), host(bg)
 
 
+@pytest.mark.parametrize("prec", [argus.FP32, argus.FP64, argus.BF16X3])
 @pytest.mark.parametrize("D,mode,tiles", [(0, argus.FIT_GLOBAL, (1, 1)),
                                           (2, argus.FIT_GLOBAL, (3, 2)),
                                           (0, argus.FIT_PER_TILE, (2, 2))])
-def test_fit_exact_recovery(ctx, D, mode, tiles):
+def test_fit_exact_recovery(ctx, D, mode, tiles, prec):
     h = 5
     spec = _spec(half_width=h, spatial_degree=D, bg_degree=D, tiles_x=tiles[0],
-                 tiles_y=tiles[1], mode=mode)
+                 tiles_y=tiles[1], mode=mode, precision=prec)
     os_ = _ospec(spec)
     H, W = 150, 170
     ref = _star_ref(W, H, 60, 50 + D)
@@ -236,13 +238,19 @@ def test_fit_exact_recovery(ctx, D, mode, tiles):
     assert err <= EXACT_STAMP_TOL[spec.precision]
     assert np.allclose(bg, o_bg, rtol=1e-3, atol=0.05)
     # photometric ratio: the kernel sum is the B_0 coefficient
-    assert np.allclose(co[:, 0], [a[0] for a in a_true], rtol=1e-5)
+    assert np.allclose(co[:, 0], [a[0] for a in a_true], rtol=1e-5 if prec != argus.BF16X3 else 1e-2)
 
 
+NOISY_STAMP_TOL = {argus.FP32: 1e-4, argus.FP64: 1e-5, argus.BF16X3: 0.2}
+NOISY_CHI2_TOL = {argus.FP32: 1e-5, argus.FP64: 1e-7, argus.BF16X3: 0.02}
+
+
+@pytest.mark.parametrize("prec", [argus.FP32, argus.FP64, argus.BF16X3])
 @pytest.mark.parametrize("D,h,tiles", [(0, 7, (1, 1)), (2, 7, (4, 3)), (2, 10, (2, 2))])
-def test_fit_parity_noisy(ctx, D, h, tiles):
+def test_fit_parity_noisy(ctx, D, h, tiles, prec):
     planes = _noisy_pair(333, 280, 60 + D + h, n_stars=250)
-    spec = _spec(half_width=h, spatial_degree=D, bg_degree=D, tiles_x=tiles[0], tiles_y=tiles[1])
+    spec = _spec(half_width=h, spatial_degree=D, bg_degree=D, tiles_x=tiles[0], tiles_y=tiles[1],
+                 precision=prec)
     os_ = _ospec(spec)
     co, nf, st, stamps, bg = _fit(ctx, spec, planes)
     oco, ost, onf = oracle.fit_kernel(*planes, os_)
@@ -250,11 +258,11 @@ def test_fit_parity_noisy(ctx, D, h, tiles):
     assert nf[0] == onf[0]
     o_stamps, o_bg = oracle.expand_kernel(oco, os_)
     err = np.abs(stamps - o_stamps).max() / np.abs(o_stamps).max()
-    print("noisy stamp error", err, "coef rel", np.abs(co - oco).max() / np.abs(oco).max())
-    assert err <= 1e-4
     gc2 = oracle.chi2(*planes, os_, co)
     oc2 = oracle.chi2(*planes, os_, oco)
-    assert abs(gc2[0] / oc2[0] - 1) <= 1e-5
+    print(f"prec {prec} D {D} h {h}: stamp error {err:.3e}, chi2 ratio - 1 {gc2[0] / oc2[0] - 1:.3e}")
+    assert err <= NOISY_STAMP_TOL[prec]
+    assert abs(gc2[0] / oc2[0] - 1) <= NOISY_CHI2_TOL[prec]
 
 
 def test_fit_per_tile_parity(ctx):
@@ -293,14 +301,15 @@ def test_fit_is_deterministic(ctx):
     assert np.array_equal(a, b)
 
 
-def test_fit_subtract_chain_parity(ctx):
+@pytest.mark.parametrize("prec", [argus.FP32, argus.FP64])
+def test_fit_subtract_chain_parity(ctx, prec):
     """GPU fit + expand + subtract against the oracle chain on the same noisy
     frames: the difference image agrees to RMS 1e-4 of the per-pixel sigma."""
     import torch
     for D, h, tiles in [(0, 7, (1, 1)), (2, 10, (4, 4))]:
         planes = _noisy_pair(512, 480, 300 + D, n_stars=700)
         spec = _spec(half_width=h, spatial_degree=D, bg_degree=D, tiles_x=tiles[0],
-                     tiles_y=tiles[1])
+                     tiles_y=tiles[1], precision=prec)
         os_ = _ospec(spec)
         co, nf, st, stamps, bg = _fit(ctx, spec, planes)
         g = _run_subtract(ctx, spec, stamps, bg, planes)
@@ -313,7 +322,7 @@ def test_fit_subtract_chain_parity(ctx):
         ok = oM == 0
         err = (gD[ok] - oD[ok]) / np.sqrt(oV[ok])
         rms, mx = np.sqrt(np.mean(err ** 2)), np.abs(err).max()
-        print(f"chain D={D} h={h}: RMS {rms:.3e} max {mx:.3e} sigma")
+        print(f"chain prec {prec} D={D} h={h}: RMS {rms:.3e} max {mx:.3e} sigma")
         assert rms <= 1e-4 and mx <= 1e-2
 
 
