@@ -369,6 +369,28 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
     fa.h = spec->half_width;
     fa.nb = argus_nbasis(spec);
     fa.nplanes = argus_nplanes(spec);
+    // planes to waves, longest first onto the least loaded wave; a plane costs
+    // its row filter plus one column filter per basis function it feeds
+    {
+        int cost[ARGUS_MAX_PLANES], load[4] = {0, 0, 0, 0}, nin[4] = {0, 0, 0, 0};
+        int p = 0;
+        for (int g = 0; g < spec->n_gauss; ++g)
+            for (int i = 0; i <= spec->degree[g]; ++i, ++p) cost[p] = 1 + (spec->degree[g] - i + 1);
+        for (int w = 0; w < 4; ++w)
+            for (int j = 0; j < 4; ++j) fa.plist[w][j] = -1;
+        bool used[ARGUS_MAX_PLANES] = {};
+        for (int n = 0; n < fa.nplanes; ++n) {
+            int best = -1;
+            for (int q = 0; q < fa.nplanes; ++q)
+                if (!used[q] && (best < 0 || cost[q] > cost[best])) best = q;
+            int w = -1;
+            for (int c = 0; c < 4; ++c)
+                if (nin[c] < 4 && (w < 0 || load[c] < load[w])) w = c;
+            used[best] = true;
+            fa.plist[w][nin[w]++] = (int8_t)best;
+            load[w] += cost[best];
+        }
+    }
     const bool global = spec->mode == ARGUS_FIT_GLOBAL;
     fa.RX = global ? 1 : spec->tiles_x;
     fa.RY = global ? 1 : spec->tiles_y;
