@@ -211,54 +211,41 @@ struct WaveGram {
 typedef const __attribute__((address_space(4))) float *cfloat_p;
 __device__ __forceinline__ float uload(const float *p) { return *(cfloat_p)p; }
 
-// LDS carve-up of the accumulation kernel.  The per-row operand tables are
-// double-buffered: the MFMA phase of output row y-1 reads buffer (y-1)&1 while
-// the convolution of row y writes buffer y&1, with one barrier per row.
+// LDS carve-up of the accumulation kernel (4-byte words).
 template <int D, int HH>
 struct FitLds {
     static constexpr int K = 2 * HH + 1;
     static constexpr int IN = SW + 2 * HH;               // input row length
     static constexpr int INP = (IN + 3) & ~3;
-    using S = FitShape<D>;
-    float *rowbuf, *inrow;
-    float *cvec[2], *wx[2];
-    double *wxd[2], *wsx[2];
+    float *rowbuf, *inrow, *cvec, *wx, *wsx;
+    double *wxd, *wsxd;
     uint8_t *minrow;
     __host__ __device__ static size_t bytes(int nplanes) {
-        size_t b = ((size_t)nplanes * K * SW + 2 * INP) * 4;         // rowbuf, inrow
-        b += 2 * ((size_t)SW * CST + S::NA * SW) * 4;                 // cvec, wx
-        b = (b + 15) & ~(size_t)15;
-        b += 2 * (size_t)(S::NA + S::NRA) * SW * 8;                   // wxd, wsx
-        b += 2 * INP + 16;                                            // minrow
+        using S = FitShape<D>;
+        size_t w = (size_t)nplanes * K * SW + 2 * INP + SW * CST + (S::NA + S::NRA) * SW;
+        size_t b = w * 4 + (size_t)(S::NA + S::NRA) * SW * 8 + 2 * INP + 16;
         size_t rhs = (size_t)8 * S::NR * 32 * 8 + 256;    // end-of-kernel reuse of rowbuf
         return (b > rhs ? b : rhs) + 64;
     }
     __device__ FitLds(float *lds, int nplanes) {
+        using S = FitShape<D>;
         rowbuf = lds;                                   // [NPL][K][SW]: thread-private columns
         inrow = rowbuf + (size_t)nplanes * K * SW;      // [2][INP] double-buffered input row
-        float *f = inrow + 2 * INP;
-        for (int i = 0; i < 2; ++i) {
-            cvec[i] = f;                                // [SW][CST] raw basis convolutions
-            wx[i] = f + SW * CST;                       // [NA][SW]  w xt^a
-            f = wx[i] + S::NA * SW;
-        }
-        double *d = (double *)(((uintptr_t)f + 15) & ~(uintptr_t)15);
-        for (int i = 0; i < 2; ++i) {
-            wxd[i] = d;                                 // [NA][SW]  w xt^a (FP64)
-            wsx[i] = d + S::NA * SW;                    // [NRA][SW] w S xt^a (FP64)
-            d = wsx[i] + S::NRA * SW;
-        }
-        minrow = (uint8_t *)d;                          // [2][INP] ref mask != 0
+        cvec = inrow + 2 * INP;                         // [SW][CST] raw basis convolutions
+        wx = cvec + SW * CST;                           // [NA][SW]  w xt^a
+        wsx = wx + S::NA * SW;                          // [NRA][SW] w S xt^a
+        wxd = (double *)(((uintptr_t)(wsx + S::NRA * SW) + 15) & ~(uintptr_t)15);  // [NA][SW]
+        wsxd = wxd + S::NA * SW;                        // [NRA][SW] w S xt^a (FP64 path)
+        minrow = (uint8_t *)(wsxd + S::NRA * SW);       // [2][INP] ref mask != 0
     }
 };
 
 // One workgroup: a 64-column strip of a region, rows [ry0, ry1).  Wave w owns
-// the row-filter planes a.plist[w][*] at column x = lane (its slice of the
+// the row-filter planes w, w+4, w+8, w+12 at column x = lane (its slice of the
 // circular row buffer is private, so the row and column passes need no
-// barrier between them); wave 0 also owns the fit-set weights.  Iteration yy
-// (input row yy): store the prefetched row, prefetch the next, barrier; then
-// the row filters of row yy and column filters of output row yy-h, and the
-// MFMA moments and right-hand side of output row yy-h-1.
+// barrier between them); wave 0 also owns the fit-set weights.  Per input row:
+// write the prefetched row to LDS, prefetch the next one, barrier, row filters,
+// column filters + weights, barrier, MFMA moments and rhs of the output row.
 template <int D, int HH, int WAVE, int PREC>
 __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0, int ry1,
                          bool active, double *part) {
@@ -266,7 +253,8 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
     using L = FitLds<D, HH>;
     constexpr int K = L::K;
     const int tid = threadIdx.x, lane = tid & 63;
-    L l(lds, a.nplanes);
+    const int NPL = a.nplanes;
+    L l(lds, NPL);
     double *rhsbuf = (double *)lds;
 
     WaveGram<D, WAVE, PREC> gram;
@@ -277,15 +265,15 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
     int count = 0;
 
     // this wave's planes (wave-uniform)
-    int pl[4], k0[4], nk[4];
+    int k0[4], nk[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        pl[j] = a.plist[WAVE][j];
+        const int p = a.plist[WAVE][j];
         k0[j] = 0;
         nk[j] = 0;
-        if (pl[j] >= 0) {
+        if (p >= 0) {
             for (int k = 0; k < a.nb; ++k)
-                if (a.tab->kpl[k] == pl[j]) {
+                if (a.tab->kpl[k] == p) {
                     if (nk[j] == 0) k0[j] = k;
                     ++nk[j];
                 }
@@ -330,35 +318,34 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
         fetch_in(ry0 - HH);
         fetch_w(ry0);
     }
-    // one extra iteration drains the moments of the last output row
-    for (int yy = ry0 - HH; yy < (active ? yend + 1 : yend); ++yy) {
-        const bool inrow_ok = yy < yend;
+    for (int yy = ry0 - HH; yy < yend; ++yy) {
         const int buf = yy & 1;
-        if (inrow_ok && tid < L::IN) {
+        if (tid < L::IN) {
             l.inrow[buf * L::INP + tid] = pr;
             l.minrow[buf * L::INP + tid] = pm;
         }
         const float w_s = p_s, w_sv = p_sv, w_rv = p_rv;
         const uint8_t w_sm = p_sm;
         if (yy + 1 < yend) fetch_in(yy + 1);
-        const bool outrow = inrow_ok && yy >= ry0 + HH;      // column pass of row yy - h
+        const bool outrow = yy >= ry0 + HH;
         if (outrow) fetch_w(yy + 1 - HH);
         __syncthreads();
-        if (inrow_ok) {
-            // row filters of my planes at x = lane
-            const int slot = yy % K;
+        // row filters of my planes at x = lane
+        const int slot = yy % K;
+        {
             float win[K];
             const float *ir = l.inrow + buf * L::INP + lane;
 #pragma unroll
             for (int uu = 0; uu < K; ++uu) win[uu] = ir[2 * HH - uu];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (pl[j] >= 0) {
-                    const float *f = &a.tab->rowf[pl[j]][0];
+                const int p = a.plist[WAVE][j];
+                if (p >= 0) {
+                    const float *f = &a.tab->rowf[p][0];
                     float acc = 0.f;
 #pragma unroll
                     for (int uu = 0; uu < K; ++uu) acc += uload(f + uu) * win[uu];
-                    l.rowbuf[((size_t)pl[j] * K + slot) * SW + lane] = acc;
+                    l.rowbuf[((size_t)p * K + slot) * SW + lane] = acc;
                 }
             }
             if (WAVE == 0) {
@@ -370,18 +357,19 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
             }
         }
         if (outrow) {
-            const int y = yy - HH, ob = y & 1;
+            const int y = yy - HH;
             // column filters: rows y-h..y+h sit in slots (yy+1 .. yy+K) mod K
-            const int s0 = (yy + 1) % K;
+            int s0 = (yy + 1) % K;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (pl[j] >= 0) {
+                const int p = a.plist[WAVE][j];
+                if (p >= 0) {
                     float t[K];
 #pragma unroll
                     for (int jj = 0; jj < K; ++jj) {
                         int sl = s0 + jj;
                         sl -= sl >= K ? K : 0;
-                        t[jj] = l.rowbuf[((size_t)pl[j] * K + sl) * SW + lane];
+                        t[jj] = l.rowbuf[((size_t)p * K + sl) * SW + lane];
                     }
 #pragma unroll
                     for (int q = 0; q < 5; ++q) {
@@ -390,7 +378,7 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
                             float acc = 0.f;
 #pragma unroll
                             for (int jj = 0; jj < K; ++jj) acc += uload(f + 2 * HH - jj) * t[jj];
-                            l.cvec[ob][lane * CST + k0[j] + q] = acc;
+                            l.cvec[lane * CST + k0[j] + q] = acc;
                         }
                     }
                 }
@@ -407,29 +395,29 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
                 double xpd = 1.0;
 #pragma unroll
                 for (int e = 0; e < S::NA; ++e) {
-                    l.wx[ob][e * SW + lane] = w * xp;
-                    if (PREC == ARGUS_FP64) l.wxd[ob][e * SW + lane] = (double)w * xpd;
-                    if (e < S::NRA) l.wsx[ob][e * SW + lane] = (double)w * (double)w_s * xpd;
+                    l.wx[e * SW + lane] = w * xp;
+                    if (PREC == ARGUS_FP64) l.wxd[e * SW + lane] = (double)w * xpd;
+                    if (e < S::NRA) l.wsx[e * SW + lane] = w * w_s * xp;
+                    if (PREC == ARGUS_FP64 && e < S::NRA)
+                        l.wsxd[e * SW + lane] = (double)w * (double)w_s * xpd;
                     xp *= xt;
                     xpd *= xtd;
                 }
             }
         }
-        const int ym = yy - 1 - HH;                           // moments of row ym
-        if (ym >= ry0 && ym < ry1 && active) {
-            const int mb = ym & 1;
+        __syncthreads();
+        if (outrow) {
+            const int y = yy - HH;
             double ypw[2 * D + 1];
             {
-                double yt = (double)ym * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
+                double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
                 double yp = 1.0;
 #pragma unroll
                 for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
             }
-            gram.row(l.cvec[mb], l.wx[mb], l.wxd[mb], ypw, lane, g0, g1);
+            gram.row(l.cvec, l.wx, l.wxd, ypw, lane, g0, g1);
             {
                 const int k = lane & 31, half = lane >> 5;
-                const float *cv = l.cvec[mb];
-                const double *ws = l.wsx[mb];
                 if constexpr (PREC == ARGUS_FP64) {
                     // right-hand side in FP64: products and the 8-pixel sums
                     double ra[S::NRA];
@@ -438,9 +426,10 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int px = WAVE * 16 + half * 8 + i;
-                        const double c = (double)cv[px * CST + k] + (double)gk * (double)cv[px * CST];
+                        const double c = (double)l.cvec[px * CST + k] +
+                                         (double)gk * (double)l.cvec[px * CST];
 #pragma unroll
-                        for (int e = 0; e < S::NRA; ++e) ra[e] += ws[e * SW + px] * c;
+                        for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsxd[e * SW + px] * c;
                     }
 #pragma unroll
                     for (int e = 0; e < S::NRA; ++e)
@@ -454,9 +443,9 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int px = WAVE * 16 + half * 8 + i;
-                        const float c = cv[px * CST + k] + gk * cv[px * CST];
+                        const float c = l.cvec[px * CST + k] + gk * l.cvec[px * CST];
 #pragma unroll
-                        for (int e = 0; e < S::NRA; ++e) ra[e] += (float)ws[e * SW + px] * c;
+                        for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsx[e * SW + px] * c;
                     }
 #pragma unroll
                     for (int e = 0; e < S::NRA; ++e)
@@ -505,11 +494,11 @@ __global__ __launch_bounds__(NTHR) void fit_accum_kernel(FitArgs a) {
     const bool active = sx0 < sx1 && ry0 < ry1;    // otherwise the partial is all zeros
     const int pid = ((ry * a.RX + rx) * a.rchunks + rc) * a.spt + s;
     double *part = a.partials + (size_t)pid * a.stride;
-    // constant tail of c: 1 at index nb (background), zeros after, in both buffers
+    // constant tail of c: 1 at index nb (background), zeros after
     FitLds<D, HH> L(lds, a.nplanes);
-    for (int i = tid; i < 2 * SW * CST; i += NTHR) {
+    for (int i = tid; i < SW * CST; i += NTHR) {
         int k = i % CST;
-        if (k >= a.nb) L.cvec[i / (SW * CST)][i % (SW * CST)] = (k == a.nb) ? 1.f : 0.f;
+        if (k >= a.nb) L.cvec[i] = (k == a.nb) ? 1.f : 0.f;
     }
     switch (tid >> 6) {
         case 0: fit_wave<D, HH, 0, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
@@ -518,6 +507,7 @@ __global__ __launch_bounds__(NTHR) void fit_accum_kernel(FitArgs a) {
         default: fit_wave<D, HH, 3, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
     }
 }
+
 
 // Launch fit_accum_kernel<D, h, PREC> with its dynamic LDS size.
 template <int PREC>
