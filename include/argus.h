@@ -201,6 +201,59 @@ int argus_detect(argus_ctx *ctx, argus_dims dims,
                  float *snr, uint8_t *det_mask,
                  argus_candidate *cands, int32_t capacity, int32_t *n_cands);
 
+/* ---- batched cutouts (per-segment subtraction, Transient Alerts; Table 2) --
+ * Many target cutouts from many cameras' frames, each fit with its own
+ * spatially constant kernel and differenced, in ONE persistent launch that
+ * workgroups drain from a work queue (largest cutouts first), captured in a
+ * HIP graph.  Each cutout is treated as a standalone image of side L: its
+ * fit set, edges and footprints stay inside the cutout (the same result as
+ * argus_fit_kernel / argus_subtract / argus_detect on an L x L copy).
+ * Spec: spatial_degree = bg_degree = 0, mode GLOBAL, precision FP32,
+ * half_width 4..10.  Outputs per cutout c (device):
+ *   diff/diff_var (f32), diff_mask/det_mask (u8): L*L values at
+ *   out_offset[c], row-major with pitch L (the caller sizes the arena);
+ *   coeffs f64 [n][n_unknowns], chi2 f64 [n], n_fit i64 [n],
+ *   status i32 [n], n_cands i32 [n] (candidates of det_mask, threshold as
+ *   in argus_detect). */
+typedef struct {
+    int32_t frame;            /* index into the frame table */
+    int32_t x0, y0;           /* top-left pixel in the frame */
+    int32_t side;             /* L, 2h+2 .. 512 */
+    int64_t out_offset;       /* element offset of the cutout in the arena */
+} argus_cutout;
+
+typedef struct {              /* one registered, calibrated frame pair (device) */
+    const float *ref, *ref_var;
+    const uint8_t *ref_mask;
+    const float *sci, *sci_var;
+    const uint8_t *sci_mask;
+    int32_t width, height;
+    int64_t pitch;            /* elements, shared by the six planes */
+} argus_frame;
+
+typedef struct argus_batch argus_batch;
+
+/* Validate the HOST cutout table against n_frames frames of the given sizes
+ * (widths/heights: HOST arrays), order the work, upload it and size the
+ * workspace.  Allocates; call outside stream capture. */
+int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec,
+                     const argus_cutout *cutouts, int n_cutouts,
+                     const int32_t *frame_widths, const int32_t *frame_heights,
+                     int n_frames, argus_batch **out);
+/* Run the batch on the frames (HOST array of n_frames descriptors).  The
+ * first run times every candidate tile shape and workgroup count on these
+ * inputs (the autotuner), keeps the fastest, and captures the queue reset
+ * and the persistent kernel in a HIP graph; later runs with the same frame
+ * and output pointers replay the graph. */
+int argus_batch_run(argus_ctx *ctx, argus_batch *batch, const argus_frame *frames,
+                    float threshold, float *diff, float *diff_var, uint8_t *diff_mask,
+                    uint8_t *det_mask, double *coeffs, double *chi2, int64_t *n_fit,
+                    int32_t *status, int32_t *n_cands);
+/* Autotuner outcome: chosen candidate index, its time in ms, and the number of
+ * candidates tried (any pointer may be null). */
+int argus_batch_info(const argus_batch *batch, int *choice, float *ms, int *n_candidates);
+void argus_batch_destroy(argus_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

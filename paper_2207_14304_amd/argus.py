@@ -25,7 +25,8 @@ FP32, BF16X3, FP64 = 0, 1, 2
 SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "argus_last_error",
            "argus_ctx_set_timing", "argus_kernel_time_ms", "argus_calibrate", "argus_coadd",
            "argus_kernel_dims", "argus_fit_kernel", "argus_expand_kernel", "argus_subtract",
-           "argus_detect")
+           "argus_detect", "argus_batch_plan", "argus_batch_run", "argus_batch_info",
+           "argus_batch_destroy")
 
 
 class Dims(C.Structure):
@@ -37,6 +38,17 @@ class KernelSpec(C.Structure):
                 ("half_width", C.c_int32), ("spatial_degree", C.c_int32),
                 ("bg_degree", C.c_int32), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
                 ("mode", C.c_int32), ("precision", C.c_int32)]
+
+
+class Cutout(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32), ("side", C.c_int32),
+                ("out_offset", C.c_int64)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("ref", C.c_void_p), ("ref_var", C.c_void_p), ("ref_mask", C.c_void_p),
+                ("sci", C.c_void_p), ("sci_var", C.c_void_p), ("sci_mask", C.c_void_p),
+                ("width", C.c_int32), ("height", C.c_int32), ("pitch", C.c_int64)]
 
 
 CANDIDATE_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("snr", np.float32),
@@ -86,8 +98,16 @@ def load(path: str = LIB_PATH):
     lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
     lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 13
     lib.argus_detect.argtypes = [vp, Dims, vp, vp, vp, f32, vp, C.c_int, vp, vp, vp, i32, vp]
+    lib.argus_batch_plan.argtypes = [vp, C.POINTER(KernelSpec), C.POINTER(Cutout), C.c_int,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int,
+                                     C.POINTER(vp)]
+    lib.argus_batch_run.argtypes = [vp, vp, C.POINTER(Frame), f32] + [vp] * 9
+    lib.argus_batch_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(f32), C.POINTER(C.c_int)]
+    lib.argus_batch_destroy.argtypes = [vp]
+    lib.argus_batch_destroy.restype = None
     for name in SYMBOLS:
-        if name not in ("argus_ctx_destroy", "argus_last_error", "argus_kernel_time_ms"):
+        if name not in ("argus_ctx_destroy", "argus_last_error", "argus_kernel_time_ms",
+                        "argus_batch_destroy"):
             getattr(lib, name).restype = C.c_int
     _ = (i64,)
     _lib = lib
@@ -226,3 +246,67 @@ class Context:
             _ptr(diff_mask, torch.uint8), float(threshold), _ptr(psf, torch.float32),
             int(psf_half), _ptr(snr, torch.float32), _ptr(det_mask, torch.uint8),
             _ptr(cands, torch.uint8), int(capacity), _ptr(n_cands, torch.int32)))
+
+
+class Batch:
+    """A planned batch of cutouts (argus_batch_plan); run with Context.batch_run."""
+
+    def __init__(self, ctx: "Context", spec: KernelSpec, frame, x0, y0, side, widths, heights):
+        self.ctx = ctx
+        self.spec = spec
+        side = np.asarray(side, np.int64)
+        self.n = int(side.size)
+        self.side = side
+        self.offsets = np.concatenate([[0], np.cumsum(side * side)[:-1]]).astype(np.int64)
+        self.arena = int((side * side).sum())
+        arr = (Cutout * self.n)()
+        for i in range(self.n):
+            arr[i] = Cutout(int(frame[i]), int(x0[i]), int(y0[i]), int(side[i]),
+                            int(self.offsets[i]))
+        nf = len(widths)
+        w = (C.c_int32 * nf)(*[int(v) for v in widths])
+        h = (C.c_int32 * nf)(*[int(v) for v in heights])
+        hnd = C.c_void_p()
+        ctx._bind()
+        ctx._check(ctx.lib.argus_batch_plan(ctx.h, C.byref(spec), arr, self.n, w, h, nf,
+                                            C.byref(hnd)))
+        self.h = hnd
+        self.n_frames = nf
+
+    def info(self):
+        c, ms, n = C.c_int(), C.c_float(), C.c_int()
+        self.ctx.lib.argus_batch_info(self.h, C.byref(c), C.byref(ms), C.byref(n))
+        return c.value, ms.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.argus_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _batch_run(self, batch: Batch, frames, threshold, diff, diff_var, diff_mask, det_mask,
+               coeffs, chi2, n_fit, status, n_cands):
+    """frames: list of (ref, ref_var, ref_mask, sci, sci_var, sci_mask) device tensors."""
+    torch = self._torch
+    self._bind()
+    arr = (Frame * len(frames))()
+    for i, f in enumerate(frames):
+        d = _dims(f[0])
+        arr[i] = Frame(_ptr(f[0], torch.float32), _ptr(f[1], torch.float32),
+                       _ptr(f[2], torch.uint8), _ptr(f[3], torch.float32),
+                       _ptr(f[4], torch.float32), _ptr(f[5], torch.uint8),
+                       d.width, d.height, d.pitch)
+    self._check(self.lib.argus_batch_run(
+        self.h, batch.h, arr, float(threshold), _ptr(diff, torch.float32),
+        _ptr(diff_var, torch.float32), _ptr(diff_mask, torch.uint8), _ptr(det_mask, torch.uint8),
+        _ptr(coeffs, torch.float64), _ptr(chi2, torch.float64), _ptr(n_fit, torch.int64),
+        _ptr(status, torch.int32), _ptr(n_cands, torch.int32)))
+
+
+Context.batch_run = _batch_run

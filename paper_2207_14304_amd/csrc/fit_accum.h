@@ -247,8 +247,8 @@ struct FitLds {
 // write the prefetched row to LDS, prefetch the next one, barrier, row filters,
 // column filters + weights, barrier, MFMA moments and rhs of the output row.
 template <int D, int HH, int WAVE, int PREC>
-__device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0, int ry1,
-                         bool active, double *part) {
+__device__ void fit_wave(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
+                         int ry1, bool active, double *part) {
     using S = FitShape<D>;
     using L = FitLds<D, HH>;
     constexpr int K = L::K;
@@ -284,6 +284,10 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
     const float g0 = (lane & 15) < a.nb ? a.tab->gam[lane & 15] : 0.f;
     const float g1 = 16 + (lane & 15) < a.nb ? a.tab->gam[16 + (lane & 15)] : 0.f;
     const float gk = (lane & 31) < a.nb ? a.tab->gam[lane & 31] : 0.f;  // rhs fix-up
+    // strips of SW columns over [sx_begin, sx_end); the sums run across strips
+    const int nstrips = active ? (sx_end - sx_begin + SW - 1) / SW : 1;
+    for (int strip = 0; strip < nstrips; ++strip) {
+    const int sx0 = sx_begin + strip * SW, sx1 = min(sx0 + SW, sx_end);
     const double xtd = (double)(sx0 + lane) * a.sx - (a.sx != 0.0 ? 1.0 : 0.0);
     const float xt = (float)xtd;
 
@@ -455,6 +459,7 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx0, int sx1, int ry0
                 }
             }
         }
+    }
     }
     __syncthreads();
     gram.store(part, lane);
