@@ -1,0 +1,108 @@
+"""Pins of the surrogate oracle: convolution against scipy, gradients
+against central finite differences, Adam's first step in closed form, stamp
+selection and normalisation by brute force, and the background formula on
+in-span data."""
+import numpy as np
+import pytest
+from scipy import signal
+
+import oracle
+from oracle import surrogate as sg
+
+
+def test_conv3x3_matches_scipy_correlate():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((2, 3, 9, 8))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    out = sg.conv3x3(a, w, b)
+    for n in range(2):
+        for o in range(4):
+            ref = b[o] + sum(signal.correlate2d(a[n, c], w[o, c], mode="same") for c in range(3))
+            assert np.allclose(out[n, o], ref, rtol=1e-12, atol=1e-12)
+
+
+def _tiny():
+    rng = np.random.default_rng(1)
+    p = sg.init_params(rng, C=4, cin=2, nout=5)
+    X = rng.standard_normal((2, 3, 2, 7, 7))
+    valid = np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 1.0]])
+    tgt = rng.standard_normal((2, 5))
+    return p, X, valid, tgt
+
+
+def test_backward_matches_finite_differences():
+    p, X, valid, tgt = _tiny()
+    out, cache = sg.forward(p, X, valid)
+    g = sg.backward(p, cache, out, tgt)
+    eps = 1e-6
+    for k in p:
+        flat = p[k].reshape(-1)
+        num = np.zeros_like(flat)
+        for i in range(flat.size):
+            old = flat[i]
+            flat[i] = old + eps
+            lp = sg.loss(sg.forward(p, X, valid)[0], tgt)
+            flat[i] = old - eps
+            lm = sg.loss(sg.forward(p, X, valid)[0], tgt)
+            flat[i] = old
+            num[i] = (lp - lm) / (2 * eps)
+        ana = g[k].reshape(-1)
+        scale = max(np.abs(num).max(), 1e-12)
+        assert np.abs(ana - num).max() <= 1e-7 * max(scale, 1.0), k
+
+
+def test_invalid_stamps_do_not_contribute():
+    p, X, valid, tgt = _tiny()
+    out, _ = sg.forward(p, X, valid)
+    X2 = X.copy()
+    X2[0, 2] = 123.0                       # stamp 2 of tile 0 is invalid
+    out2, _ = sg.forward(p, X2, valid)
+    assert np.array_equal(out, out2)
+
+
+def test_adam_first_step_closed_form():
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -0.25, 0.0])}
+    st = {}
+    sg.adam_step(p, g, st, lr=0.1)
+    exp = np.array([1.0 - 0.1 * 0.5 / (0.5 + 1e-8), -2.0 + 0.1 * 0.25 / (0.25 + 1e-8), 3.0])
+    assert np.allclose(p["w"], exp, rtol=1e-12)
+    assert st["t"] == 1
+
+
+def test_stamp_selection_and_normalisation():
+    H, W = 60, 70
+    ref = np.full((H, W), 10.0)
+    var = np.full((H, W), 1.0)
+    peaks = [(20, 20, 500.0), (30, 40, 900.0), (3, 30, 2000.0), (40, 22, 900.0), (45, 50, 300.0)]
+    for y, x, v in peaks:
+        ref[y, x] = v
+    rm = np.zeros((H, W), np.uint8)
+    sm = np.zeros((H, W), np.uint8)
+    sm[45 + 3, 50 - 2] = 1                       # masks the stamp around (45, 50)
+    cs = sg.select_stamps(ref, var, rm, sm, 1, 1, r=4, S=3)
+    # (3,30) is too close to the edge; (45,50) is masked; equal peaks: raster first
+    assert cs == [[(30, 40), (40, 22), (20, 20)]]
+    sci = 2.0 * ref + 7.0
+    Xs, v = sg.make_stamps(ref, sci, cs, r=4, S=3)
+    assert v.tolist() == [[1.0, 1.0, 1.0]]
+    assert np.allclose(Xs[0, :, 0].sum(axis=(1, 2)), 1.0)
+    assert np.allclose(Xs[0, :, 1], 2.0 * Xs[0, :, 0])
+    st = np.arange(25.0).reshape(5, 5)
+    b = np.r_[st[0], st[-1], st[1:-1, 0], st[1:-1, -1]]
+    assert sg.border_median(st) == np.median(b)
+
+
+def test_background_given_kernel_in_span():
+    from test_oracle_pins import _star_ref
+    H, W = 60, 64
+    ref = _star_ref(W, H, 15, 9)
+    spec = oracle.KernelSpec(half_width=4)
+    B = oracle.basis(spec)
+    K = 1.03 * B[0] + 0.02 * B[3]
+    sci = signal.convolve2d(ref, K, mode="same") - 17.5
+    one = np.ones((H, W))
+    z = np.zeros((H, W), np.uint8)
+    bg = sg.background_given_kernel(K, ref, one, z, sci, one, z, 4)
+    assert bg == pytest.approx(-17.5, abs=1e-9)
