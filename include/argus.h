@@ -175,15 +175,18 @@ int argus_expand_kernel(argus_ctx *ctx, const argus_kernel_spec *spec,
  *   V = var_S + sum_{u,v} K_p(u,v)^2 var_R(x-u, y-v)
  * diff_mask = sci_mask | EDGE (within h of the border) | FOOT (any ref_mask
  * bit in the footprint); D = V = 0 where diff_mask != 0.
- * chi2 f64 [n_solves] (nullable): sum over the fit set of D^2/(var_S+var_R);
- * n_chi2 i64 [n_solves] (nullable): size of that set.  Stamps and bg as
- * written by argus_expand_kernel (any caller kernel works, e.g. a delta). */
+ * Over each solve's fit set (diff_mask == 0 and var_S + var_R > 0), with
+ * w = 1/(var_S + var_R), FP64 sums (each output f64/i64 [n_solves], nullable):
+ * chi2 = sum w D^2, n_chi2 = the set's size, sum_wd = sum w D, sum_w = sum w
+ * (the last two give the weighted least-squares background correction
+ * sum_wd/sum_w for a caller-supplied kernel).  Stamps and bg as written by
+ * argus_expand_kernel (any caller kernel works, e.g. a delta). */
 int argus_subtract(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
                    const float *stamps, const float *bg,
                    const float *ref, const float *ref_var, const uint8_t *ref_mask,
                    const float *sci, const float *sci_var, const uint8_t *sci_mask,
                    float *diff, float *diff_var, uint8_t *diff_mask,
-                   double *chi2, int64_t *n_chi2);
+                   double *chi2, int64_t *n_chi2, double *sum_wd, double *sum_w);
 
 /* ---- detection (Transient Alerts: candidates from the subtraction) --------
  * snr = D/sqrt(V) where diff_mask == 0 and V > 0, else 0 (f32, nullable);
@@ -208,7 +211,8 @@ int argus_detect(argus_ctx *ctx, argus_dims dims,
  * HIP graph.  Each cutout is treated as a standalone image of side L: its
  * fit set, edges and footprints stay inside the cutout (the same result as
  * argus_fit_kernel / argus_subtract / argus_detect on an L x L copy).
- * Spec: spatial_degree = bg_degree = 0, mode GLOBAL, precision FP32,
+ * Spec: spatial_degree = bg_degree = 0, mode GLOBAL, precision FP32 or
+ * FP64 (row moments; FP64 for small, poorly conditioned cutouts),
  * half_width 4..10.  Outputs per cutout c (device):
  *   diff/diff_var (f32), diff_mask/det_mask (u8): L*L values at
  *   out_offset[c], row-major with pitch L (the caller sizes the arena);
@@ -253,6 +257,80 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *batch, const argus_frame *frame
  * candidates tried (any pointer may be null). */
 int argus_batch_info(const argus_batch *batch, int *choice, float *ms, int *n_candidates);
 void argus_batch_destroy(argus_batch *batch);
+
+/* ---- learned kernel surrogate -------------------------------------------
+ * The paper has no learned component.  This one predicts, per tile, the
+ * coefficients of the kernel model above (the constant-kernel form of the
+ * fit in the difference-imaging step) from paired star stamps; the plain
+ * least-squares fit stays the fallback and the judge (chi^2/dof).
+ * Network, shared by every stamp pair of a tile: four 3x3 'same'
+ * convolutions (zero padding, cross-correlation) 2 -> 32 -> 32 -> 32 -> 32
+ * with bias and ReLU, BF16 weights and activations, FP32 accumulation on
+ * MFMA; a spatial mean; the mean over the tile's valid stamps; an FP32
+ * linear head to the 31 kernel coefficients.  Loss: mean squared error.
+ * Parameters (FP32 master, argus_cnn_n_params floats): per layer the weights
+ * [32][9][c_in] (tap = 3 (dy+1) + (dx+1)) then the 32 biases, then the head
+ * [31][32] and its 31 biases.  Adam (0.9, 0.999, 1e-8) updates the master.
+ * Stamps X are bf16 bit patterns [T][64][31*31][2] (reference, science),
+ * valid u8 [T][64].  All device pointers unless marked HOST; calls enqueue on
+ * the context's stream.  The handle owns its buffers (activations for
+ * max_tiles tiles) until argus_cnn_destroy; one handle serves one stream. */
+typedef struct argus_cnn argus_cnn;
+int  argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out);
+void argus_cnn_destroy(argus_cnn *cnn);
+int  argus_cnn_n_params(const argus_cnn *cnn);
+/* HOST copies of the FP32 master parameters; setting them resets Adam. */
+int  argus_cnn_set_weights(argus_ctx *ctx, argus_cnn *cnn, const float *host_params);
+int  argus_cnn_get_weights(argus_ctx *ctx, argus_cnn *cnn, float *host_params);
+/* HOST copy of the gradients of the last train step (before its update). */
+int  argus_cnn_get_grads(argus_ctx *ctx, argus_cnn *cnn, float *host_grads);
+/* out f32 [T][31] (device). */
+int  argus_cnn_forward(argus_ctx *ctx, argus_cnn *cnn, const uint16_t *X, const uint8_t *valid,
+                       int T, float *out);
+/* One forward + backward + Adam step on T tiles; target f32 [T][31];
+ * *loss (device f64) receives the mean squared error before the update. */
+int  argus_cnn_train_step(argus_ctx *ctx, argus_cnn *cnn, const uint16_t *X,
+                          const uint8_t *valid, const float *target, int T, float lr,
+                          double *loss);
+/* CNN outputs f32 [n_solves][n_basis] -> coefficients f64
+ * [n_solves][n_basis + 1] (constant kernel and background, the layout of
+ * argus_fit_kernel with spatial_degree = bg_degree = 0) with zero background. */
+int  argus_surrogate_coeffs(argus_ctx *ctx, int n_solves, int n_basis, const float *cnn_out,
+                            double *coeffs);
+/* Acceptance of the surrogate per solve.  From argus_subtract run with the
+ * surrogate's kernel and zero background (chi2_0, n_0, sum_wd, sum_w), the
+ * weighted least-squares background b = sum_wd/sum_w gives
+ * chi2_s = chi2_0 - sum_wd^2/sum_w on n_0 - 1 degrees of freedom.  The tile
+ * keeps the surrogate where chi2_s/(n_0 - 1) <= factor * r_p, with r_p the
+ * plain fit's chi2/(n - n_basis - 1) (plain_chi2, plain_n) or, when those
+ * are null, the caller's ref_chi2_dof.  coeffs_out f64 [n][n_basis + 1]: the
+ * surrogate's kernel and b where accepted, else plain_coeffs (NaN when
+ * null); chi2_dof f64 [n] = chi2_s/(n_0 - 1); accepted i32 [n] = 1/0. */
+int  argus_surrogate_select(argus_ctx *ctx, int n_solves, int n_basis, const double *sur_coeffs,
+                            const double *chi2_0, const int64_t *n_0, const double *sum_wd,
+                            const double *sum_w, const double *plain_coeffs,
+                            const double *plain_chi2, const int64_t *plain_n,
+                            double ref_chi2_dof, double factor, double *coeffs_out,
+                            double *chi2_dof, int32_t *accepted);
+/* Surrogate inputs of a tiled frame pair: per tile (raster order) the
+ * positive reference local maxima (strictly above earlier 8-neighbours in
+ * raster order, >= later ones) whose (2 half + 1)^2 stamp lies in the frame
+ * are ranked brightest first (raster order on ties); walking down the
+ * ranking, a candidate is kept when its stamp is unmasked in both frames and
+ * (peak - border median of its reference stamp) / sqrt(ref_var at the peak)
+ * >= snr_min (FP32), until stamps_per_tile are kept.  Each kept pair loses
+ * its border medians; both are multiplied by 100 / (the reference stamp's
+ * remaining sum).  X bf16 bits [T][stamps_per_tile][(2 half+1)^2][2]
+ * (reference, science), valid u8 [T][stamps_per_tile]; unused slots are zero
+ * with valid = 0.  The ranking holds the brightest <= 2048 candidates of a
+ * tile; *overflow (device i32, caller-cleared) counts tiles whose walk ran
+ * out of retained candidates while dimmer ones had been dropped (their
+ * selection can then differ from the definition). */
+int  argus_extract_stamps(argus_ctx *ctx, argus_dims dims, const float *ref,
+                          const float *ref_var, const uint8_t *ref_mask, const float *sci,
+                          const uint8_t *sci_mask, int tiles_x, int tiles_y, float snr_min,
+                          int stamps_per_tile, int half, uint16_t *X, uint8_t *valid,
+                          int32_t *overflow);
 
 #ifdef __cplusplus
 }

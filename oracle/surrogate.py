@@ -5,12 +5,13 @@ stack of paired star stamps of one sub-tile to the kernel coefficients, with
 the plain least-squares fit as the fallback.  Written here from its
 definition, in numpy float64:
 
-* stamp selection - up to S reference local maxima per tile (strictly above
-  earlier 8-neighbours in raster order, >= later ones), brightest first with
-  raster order breaking ties, whose reference peak SNR is >= snr_min, whose
-  (2r+1)^2 stamp lies inside the frame and whose stamp is unmasked in both
-  frames.  Each stamp has its border median subtracted; both stamps are
-  divided by the background-subtracted reference stamp sum;
+* stamp selection - up to S positive reference local maxima per tile
+  (strictly above earlier 8-neighbours in raster order, >= later ones),
+  brightest first with raster order breaking ties, whose (2r+1)^2 stamp
+  lies inside the frame and is unmasked in both frames, and whose peak is
+  at least snr_min noise sigmas above the reference stamp's border median.  Each stamp has its border median subtracted; both stamps are
+  divided by the background-subtracted reference stamp sum and scaled by a
+  fixed 100;
 * network - four 3x3 'same' convolutions (zero padding, cross-correlation)
   2 -> C -> C -> C -> C channels with bias and ReLU, a spatial mean, a mean
   over the valid stamps, and a linear head to the nb kernel coefficients;
@@ -31,12 +32,24 @@ from . import core
 # ------------------------------------------------------------------ stamps
 def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64,
                   snr_min=10.0):
-    """Per tile (raster order of tiles) a list of up to S (y, x) stamp centres."""
+    """Per tile (raster order of tiles) a list of up to S (y, x) stamp centres.
+
+    Candidates are positive reference local maxima (strictly above the
+    8-neighbours earlier in raster order, >= the later ones) whose
+    (2r+1)^2 stamp lies inside the frame, ranked brightest first with raster
+    order breaking ties.  Walking down the ranking a candidate is kept when
+    its stamp is unmasked in both frames and (peak - border median of its
+    reference stamp) / sqrt(var at the peak) >= snr_min; the walk stops at S.
+    That test decides an integer (which stamps are kept), so it is taken in
+    float32, the precision of the frames: the median averages the middle
+    pair in float32, and the division and square root round correctly."""
     ref = np.asarray(ref, np.float64)
+    r32 = np.asarray(ref, np.float32)
+    v32 = np.asarray(ref_var, np.float32)
     H, W = ref.shape
     pad = np.full((H + 2, W + 2), -np.inf)
     pad[1:-1, 1:-1] = ref
-    lm = np.ones((H, W), bool)
+    lm = ref > 0
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
             if dx == 0 and dy == 0:
@@ -44,25 +57,38 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
             nb = pad[1 + dy:H + 1 + dy, 1 + dx:W + 1 + dx]
             earlier = dy < 0 or (dy == 0 and dx < 0)
             lm &= (ref > nb) if earlier else (ref >= nb)
-    with np.errstate(all="ignore"):
-        snr = np.where(np.asarray(ref_var) > 0, ref / np.sqrt(ref_var), 0.0)
-    lm &= snr >= snr_min
     bad = (np.asarray(ref_mask) != 0) | (np.asarray(sci_mask) != 0)
     out = []
     for (y0, y1) in core.tile_bounds(H, tiles_y):
         for (x0, x1) in core.tile_bounds(W, tiles_x):
             ys, xs = np.nonzero(lm[y0:y1, x0:x1])
             ys, xs = ys + y0, xs + x0
+            inside = (ys >= r) & (xs >= r) & (ys < H - r) & (xs < W - r)
+            cand = sorted(zip(ys[inside], xs[inside]), key=lambda p: (-ref[p[0], p[1]],
+                                                                       p[0] * W + p[1]))
             keep = []
-            for y, x in zip(ys, xs):
-                if y < r or x < r or y >= H - r or x >= W - r:
-                    continue
+            for y, x in cand:
+                if len(keep) == S:
+                    break
                 if bad[y - r:y + r + 1, x - r:x + r + 1].any():
                     continue
-                keep.append((y, x))
-            keep.sort(key=lambda p: (-ref[p[0], p[1]], p[0] * W + p[1]))
-            out.append(keep[:S])
+                m = border_median32(r32[y - r:y + r + 1, x - r:x + r + 1])
+                v = v32[y, x]
+                if not v > 0:
+                    continue
+                if (r32[y, x] - m) / np.sqrt(v) >= np.float32(snr_min):
+                    keep.append((y, x))
+            out.append(keep)
     return out
+
+
+def border_median32(st):
+    """Median of a stamp's border in float32 (middle pair averaged in float32)."""
+    b = np.sort(np.concatenate([st[0, :], st[-1, :], st[1:-1, 0], st[1:-1, -1]]).astype(np.float32))
+    k = b.size
+    if k % 2:
+        return b[k // 2]
+    return (b[k // 2 - 1] + b[k // 2]) * np.float32(0.5)
 
 
 def border_median(st):
@@ -70,8 +96,16 @@ def border_median(st):
     return np.median(b)
 
 
-def make_stamps(ref, sci, centres, r=15, S=64):
-    """Input tensor [T][S][2][2r+1][2r+1] and validity [T][S] for the centres."""
+STAMP_SCALE = 100.0
+
+
+def make_stamps(ref, sci, centres, r=15, S=64, scale=STAMP_SCALE):
+    """Input tensor [T][S][2][2r+1][2r+1] and validity [T][S] for the centres.
+
+    Both stamps lose their border medians and are divided by the reference
+    stamp's remaining sum, then multiplied by a fixed scale (100) that puts
+    the network's inputs near unit size (a 31x31 stamp of unit sum has values
+    of order 1e-3, below what BF16 activations resolve next to O(0.1) biases)."""
     ref = np.asarray(ref, np.float64)
     sci = np.asarray(sci, np.float64)
     T = len(centres)
@@ -87,8 +121,8 @@ def make_stamps(ref, sci, centres, r=15, S=64):
             tot = rs.sum()
             if not tot > 0:
                 continue
-            X[t, s, 0] = rs / tot
-            X[t, s, 1] = ss / tot
+            X[t, s, 0] = scale * rs / tot
+            X[t, s, 1] = scale * ss / tot
             valid[t, s] = 1.0
     return X, valid
 
@@ -203,3 +237,36 @@ def background_given_kernel(stamp, ref, ref_var, ref_mask, sci, sci_var, sci_mas
 def accept(chi2_surrogate, dof_surrogate, chi2_plain, dof_plain, factor=1.02):
     """The surrogate is kept where its chi^2/dof is within factor of the plain fit's."""
     return (chi2_surrogate / dof_surrogate) <= factor * (chi2_plain / dof_plain)
+
+
+def select_per_tile(kernel_coeffs, plain_coeffs, plain_chi2, plain_n, ref, ref_var, ref_mask,
+                    sci, sci_var, sci_mask, spec, factor=1.02):
+    """Per tile of a PER_TILE constant-kernel spec: the weighted least-squares
+    background given the surrogate's kernel (bg = argmin sum w (D0 - bg)^2 over
+    the tile's fit set, D0 the difference with zero background), its chi^2 on
+    n - 1 degrees of freedom, and the acceptance rule against the plain fit's
+    chi^2/(n - n_unknowns).  Returns (coeffs [n][nb + 1], chi2_dof [n],
+    accepted [n])."""
+    kc = np.asarray(kernel_coeffs, np.float64)
+    n, nb = kc.shape
+    co0 = np.concatenate([kc, np.zeros((n, 1))], 1)
+    stamps, _ = core.expand_kernel(co0, spec)
+    D0, _, dmask, _, _ = core.subtract(stamps, np.zeros((n, 1)), ref, ref_var, ref_mask, sci,
+                                       sci_var, sci_mask, spec)
+    phi = core.fit_set(ref_mask, sci_mask, ref_var, sci_var, spec.half_width)
+    with np.errstate(all="ignore"):
+        w = np.where(phi, 1.0 / (np.asarray(sci_var, np.float64) + ref_var), 0.0)
+    H, W = D0.shape
+    out = np.zeros((n, nb + 1))
+    rs = np.zeros(n)
+    acc = np.zeros(n, bool)
+    for t, (x0, x1, y0, y1) in enumerate(core._solve_regions(spec, W, H)):
+        sel = phi[y0:y1, x0:x1]
+        wt = w[y0:y1, x0:x1][sel]
+        d = D0[y0:y1, x0:x1][sel]
+        bg = float((wt * d).sum() / wt.sum())
+        chi2 = float((wt * (d - bg) ** 2).sum())
+        rs[t] = chi2 / (sel.sum() - 1)
+        acc[t] = accept(chi2, sel.sum() - 1, plain_chi2[t], plain_n[t] - (nb + 1), factor)
+        out[t] = np.r_[kc[t], bg] if acc[t] else plain_coeffs[t]
+    return out, rs, acc

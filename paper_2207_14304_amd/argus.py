@@ -26,7 +26,10 @@ SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "arg
            "argus_ctx_set_timing", "argus_kernel_time_ms", "argus_calibrate", "argus_coadd",
            "argus_kernel_dims", "argus_fit_kernel", "argus_expand_kernel", "argus_subtract",
            "argus_detect", "argus_batch_plan", "argus_batch_run", "argus_batch_info",
-           "argus_batch_destroy")
+           "argus_batch_destroy", "argus_cnn_create", "argus_cnn_destroy",
+           "argus_cnn_n_params", "argus_cnn_set_weights", "argus_cnn_get_weights",
+           "argus_cnn_get_grads", "argus_cnn_forward", "argus_cnn_train_step",
+           "argus_surrogate_coeffs", "argus_surrogate_select", "argus_extract_stamps")
 
 
 class Dims(C.Structure):
@@ -96,7 +99,7 @@ def load(path: str = LIB_PATH):
     lib.argus_kernel_dims.argtypes = [C.POINTER(KernelSpec), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 9
     lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
-    lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 13
+    lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 15
     lib.argus_detect.argtypes = [vp, Dims, vp, vp, vp, f32, vp, C.c_int, vp, vp, vp, i32, vp]
     lib.argus_batch_plan.argtypes = [vp, C.POINTER(KernelSpec), C.POINTER(Cutout), C.c_int,
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int,
@@ -105,9 +108,23 @@ def load(path: str = LIB_PATH):
     lib.argus_batch_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(f32), C.POINTER(C.c_int)]
     lib.argus_batch_destroy.argtypes = [vp]
     lib.argus_batch_destroy.restype = None
+    lib.argus_cnn_create.argtypes = [vp, C.c_int, C.POINTER(vp)]
+    lib.argus_cnn_destroy.argtypes = [vp]
+    lib.argus_cnn_destroy.restype = None
+    lib.argus_cnn_n_params.argtypes = [vp]
+    lib.argus_cnn_set_weights.argtypes = [vp, vp, vp]
+    lib.argus_cnn_get_weights.argtypes = [vp, vp, vp]
+    lib.argus_cnn_get_grads.argtypes = [vp, vp, vp]
+    lib.argus_cnn_forward.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+    lib.argus_cnn_train_step.argtypes = [vp, vp, vp, vp, vp, C.c_int, f32, vp]
+    lib.argus_surrogate_coeffs.argtypes = [vp, C.c_int, C.c_int, vp, vp]
+    lib.argus_surrogate_select.argtypes = [vp, C.c_int, C.c_int] + [vp] * 8 + \
+        [C.c_double, C.c_double, vp, vp, vp]
+    lib.argus_extract_stamps.argtypes = [vp, Dims, vp, vp, vp, vp, vp, C.c_int, C.c_int, f32,
+                                         C.c_int, C.c_int, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("argus_ctx_destroy", "argus_last_error", "argus_kernel_time_ms",
-                        "argus_batch_destroy"):
+                        "argus_batch_destroy", "argus_cnn_destroy"):
             getattr(lib, name).restype = C.c_int
     _ = (i64,)
     _lib = lib
@@ -226,7 +243,7 @@ class Context:
             _ptr(bg, torch.float32)))
 
     def subtract(self, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, diff,
-                 diff_var, diff_mask, chi2=None, n_chi2=None):
+                 diff_var, diff_mask, chi2=None, n_chi2=None, sum_wd=None, sum_w=None):
         torch = self._torch
         self._bind()
         self._check(self.lib.argus_subtract(
@@ -235,7 +252,8 @@ class Context:
             _ptr(ref_mask, torch.uint8), _ptr(sci, torch.float32), _ptr(sci_var, torch.float32),
             _ptr(sci_mask, torch.uint8), _ptr(diff, torch.float32),
             _ptr(diff_var, torch.float32), _ptr(diff_mask, torch.uint8),
-            _ptr(chi2, torch.float64), _ptr(n_chi2, torch.int64)))
+            _ptr(chi2, torch.float64), _ptr(n_chi2, torch.int64), _ptr(sum_wd, torch.float64),
+            _ptr(sum_w, torch.float64)))
 
     def detect(self, diff, diff_var, diff_mask, threshold, psf, psf_half, snr, det_mask, cands,
                capacity, n_cands):
@@ -310,3 +328,127 @@ def _batch_run(self, batch: Batch, frames, threshold, diff, diff_var, diff_mask,
 
 
 Context.batch_run = _batch_run
+
+
+# ---- learned kernel surrogate ----------------------------------------------
+CNN_STAMPS, CNN_HALF, CNN_NPX = 64, 15, 31 * 31
+
+
+def _surrogate_coeffs(self, cnn_out, coeffs):
+    torch = self._torch
+    self._bind()
+    n, nb = cnn_out.shape
+    self._check(self.lib.argus_surrogate_coeffs(self.h, int(n), int(nb),
+                                                _ptr(cnn_out, torch.float32),
+                                                _ptr(coeffs, torch.float64)))
+
+
+def _surrogate_select(self, sur_coeffs, chi2_0, n_0, sum_wd, sum_w, coeffs_out, chi2_dof,
+                      accepted, plain_coeffs=None, plain_chi2=None, plain_n=None,
+                      ref_chi2_dof=0.0, factor=1.02):
+    torch = self._torch
+    self._bind()
+    n, nc = sur_coeffs.shape
+    self._check(self.lib.argus_surrogate_select(
+        self.h, int(n), int(nc - 1), _ptr(sur_coeffs, torch.float64), _ptr(chi2_0, torch.float64),
+        _ptr(n_0, torch.int64), _ptr(sum_wd, torch.float64), _ptr(sum_w, torch.float64),
+        _ptr(plain_coeffs, torch.float64), _ptr(plain_chi2, torch.float64),
+        _ptr(plain_n, torch.int64), float(ref_chi2_dof), float(factor),
+        _ptr(coeffs_out, torch.float64), _ptr(chi2_dof, torch.float64),
+        _ptr(accepted, torch.int32)))
+
+
+def _extract_stamps(self, ref, ref_var, ref_mask, sci, sci_mask, tiles_x, tiles_y, snr_min, X,
+                    valid, overflow, stamps_per_tile=CNN_STAMPS, half=CNN_HALF):
+    """X: bf16 device tensor [T][S][(2 half+1)^2][2]; valid u8 [T][S]; overflow i32 [1]."""
+    torch = self._torch
+    self._bind()
+    if X.dtype != torch.bfloat16 or not X.is_contiguous():
+        raise TypeError("X must be a contiguous bfloat16 tensor")
+    self._check(self.lib.argus_extract_stamps(
+        self.h, _dims(ref), _ptr(ref, torch.float32), _ptr(ref_var, torch.float32),
+        _ptr(ref_mask, torch.uint8), _ptr(sci, torch.float32), _ptr(sci_mask, torch.uint8),
+        int(tiles_x), int(tiles_y), float(snr_min), int(stamps_per_tile), int(half),
+        X.data_ptr(), _ptr(valid, torch.uint8), _ptr(overflow, torch.int32)))
+
+
+Context.surrogate_coeffs = _surrogate_coeffs
+Context.surrogate_select = _surrogate_select
+Context.extract_stamps = _extract_stamps
+
+
+class CNN:
+    """An argus_cnn handle: the surrogate network's parameters, Adam state and
+    activation buffers for up to max_tiles tiles of 64 stamp pairs."""
+
+    def __init__(self, ctx: "Context", max_tiles: int):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._bind()
+        ctx._check(ctx.lib.argus_cnn_create(ctx.h, int(max_tiles), C.byref(h)))
+        self.h = h
+        self.max_tiles = int(max_tiles)
+        self.n_params = int(ctx.lib.argus_cnn_n_params(h))
+
+    def _host(self, fn, arr=None):
+        a = np.empty(self.n_params, np.float32) if arr is None else arr
+        self.ctx._bind()
+        self.ctx._check(fn(self.ctx.h, self.h, a.ctypes.data))
+        return a
+
+    def set_weights(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        self._host(self.ctx.lib.argus_cnn_set_weights, p)
+
+    def get_weights(self):
+        return self._host(self.ctx.lib.argus_cnn_get_weights)
+
+    def get_grads(self):
+        return self._host(self.ctx.lib.argus_cnn_get_grads)
+
+    def forward(self, X, valid, out):
+        torch = self.ctx._torch
+        self.ctx._bind()
+        T = int(valid.shape[0])
+        self.ctx._check(self.ctx.lib.argus_cnn_forward(
+            self.ctx.h, self.h, _ptr(X, torch.bfloat16), _ptr(valid, torch.uint8), T,
+            _ptr(out, torch.float32)))
+
+    def train_step(self, X, valid, target, lr, loss):
+        torch = self.ctx._torch
+        self.ctx._bind()
+        T = int(valid.shape[0])
+        self.ctx._check(self.ctx.lib.argus_cnn_train_step(
+            self.ctx.h, self.h, _ptr(X, torch.bfloat16), _ptr(valid, torch.uint8),
+            _ptr(target, torch.float32), T, float(lr), _ptr(loss, torch.float64)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.argus_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_param_layout(C_=32, cin=2, nout=31):
+    """Slices of the flat parameter vector: per layer w [32][9][c_in] and b [32],
+    then the head [nout][32] and its nout biases."""
+    out, off = {}, 0
+    ch = [cin, C_, C_, C_, C_]
+    for l in range(4):
+        n = ch[l + 1] * 9 * ch[l]
+        out[f"w{l}"] = (slice(off, off + n), (ch[l + 1], 9, ch[l]))
+        off += n
+        out[f"b{l}"] = (slice(off, off + ch[l + 1]), (ch[l + 1],))
+        off += ch[l + 1]
+    out["hw"] = (slice(off, off + nout * C_), (nout, C_))
+    off += nout * C_
+    out["hb"] = (slice(off, off + nout), (nout,))
+    off += nout
+    return out, off

@@ -88,7 +88,8 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                     const float *stamps, const float *bg, const float *ref,
                     const float *ref_var, const uint8_t *ref_mask, const float *sci,
                     const float *sci_var, const uint8_t *sci_mask, float *diff,
-                    float *diff_var, uint8_t *diff_mask, double *chi2, int64_t *n_chi2);
+                    float *diff_var, uint8_t *diff_mask, double *chi2, int64_t *n_chi2,
+                    double *sum_wd, double *sum_w);
 int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
                   const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
                   uint8_t *det, argus_candidate *cands, int32_t cap, int32_t *n_cands);

@@ -162,7 +162,7 @@ __device__ int solve_small(const double *G, const double *R, double cnt, int n, 
     return ARGUS_OK;
 }
 
-template <int HH, int TILE>
+template <int HH, int TILE, int PREC>
 __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
     using BL = BatchLds<HH, TILE>;
     constexpr int K = BL::K, TH = BL::TH, TW = BL::TW, MW = BL::MW;
@@ -205,10 +205,10 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
     }
     __syncthreads();
     switch (wave) {
-        case 0: argus_fit::fit_wave<0, HH, 0, ARGUS_FP32>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
-        case 1: argus_fit::fit_wave<0, HH, 1, ARGUS_FP32>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
-        case 2: argus_fit::fit_wave<0, HH, 2, ARGUS_FP32>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
-        default: argus_fit::fit_wave<0, HH, 3, ARGUS_FP32>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
+        case 0: argus_fit::fit_wave<0, HH, 0, PREC>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
+        case 1: argus_fit::fit_wave<0, HH, 1, PREC>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
+        case 2: argus_fit::fit_wave<0, HH, 2, PREC>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
+        default: argus_fit::fit_wave<0, HH, 3, PREC>(fa, lds, HH, L - HH, HH, L - HH, true, part); break;
     }
     __syncthreads();
     // ---- solve, expand the stamp ----
@@ -374,7 +374,7 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
     __syncthreads();
 }
 
-template <int HH, int TILE>
+template <int HH, int TILE, int PREC>
 __global__ __launch_bounds__(NTHR) void batch_kernel(BatchArgs a) {
     extern __shared__ float lds[];
     __shared__ int s_item;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(NTHR) void batch_kernel(BatchArgs a) {
         const int it = s_item;
         __syncthreads();
         if (it >= a.n) break;                       // every wave reaches this exit
-        process_cutout<HH, TILE>(a, a.order[it], lds);
+        process_cutout<HH, TILE, PREC>(a, a.order[it], lds);
     }
 }
 
@@ -395,26 +395,29 @@ constexpr int N_CAND = 6;
 constexpr int CAND_TILE[N_CAND] = {16, 16, 16, 32, 32, 32};
 constexpr int CAND_WPC[N_CAND] = {1, 2, 3, 1, 2, 3};
 
-template <int HH, int TILE>
+template <int HH, int TILE, int PREC>
 int batch_launch_t(argus_ctx *ctx, const BatchArgs &ba, int wg_per_cu, hipStream_t st) {
     size_t lds = BatchLds<HH, TILE>::bytes(ba.nplanes);
-    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)batch_kernel<HH, TILE>,
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)batch_kernel<HH, TILE, PREC>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int cus = 0;
     ARGUS_HIP_CHECK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
     int grid = std::max(1, std::min(cus * wg_per_cu, ba.n));
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, st, ba.queue);
-    hipLaunchKernelGGL((batch_kernel<HH, TILE>), dim3(grid), dim3(NTHR), lds, st, ba);
+    hipLaunchKernelGGL((batch_kernel<HH, TILE, PREC>), dim3(grid), dim3(NTHR), lds, st, ba);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
 
-int batch_launch(argus_ctx *ctx, const BatchArgs &ba, int h, int cand, hipStream_t st) {
+int batch_launch(argus_ctx *ctx, const BatchArgs &ba, int h, int prec, int cand, hipStream_t st) {
     const int tile = CAND_TILE[cand], wpc = CAND_WPC[cand];
-#define ARGUS_BH(HH)                                                                   \
-    case HH:                                                                           \
-        return tile == 16 ? batch_launch_t<HH, 16>(ctx, ba, wpc, st)                   \
-                          : batch_launch_t<HH, 32>(ctx, ba, wpc, st);
+#define ARGUS_BH(HH)                                                                          \
+    case HH:                                                                                  \
+        if (prec == ARGUS_FP64)                                                               \
+            return tile == 16 ? batch_launch_t<HH, 16, ARGUS_FP64>(ctx, ba, wpc, st)          \
+                              : batch_launch_t<HH, 32, ARGUS_FP64>(ctx, ba, wpc, st);         \
+        return tile == 16 ? batch_launch_t<HH, 16, ARGUS_FP32>(ctx, ba, wpc, st)              \
+                          : batch_launch_t<HH, 32, ARGUS_FP32>(ctx, ba, wpc, st);
     switch (h) {
         ARGUS_BH(4) ARGUS_BH(5) ARGUS_BH(6) ARGUS_BH(7) ARGUS_BH(8) ARGUS_BH(9) ARGUS_BH(10)
         default: return argus_fail(ctx, ARGUS_ESHAPE, "batch half width %d not in 4..10", h);
@@ -435,8 +438,9 @@ int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec, const argus_
     int nu, ns;
     int rc = argus_kernel_dims(spec, &nu, &ns);
     if (rc) return argus_fail(ctx, rc, "argus_batch_plan: bad kernel spec");
-    if (spec->spatial_degree != 0 || spec->mode != ARGUS_FIT_GLOBAL || spec->precision != ARGUS_FP32)
-        return argus_fail(ctx, ARGUS_ESHAPE, "batch fits use degree 0, GLOBAL, FP32");
+    if (spec->spatial_degree != 0 || spec->mode != ARGUS_FIT_GLOBAL ||
+        (spec->precision != ARGUS_FP32 && spec->precision != ARGUS_FP64))
+        return argus_fail(ctx, ARGUS_ESHAPE, "batch fits use degree 0, GLOBAL, FP32 or FP64");
     if (spec->half_width < 4 || spec->half_width > 10)
         return argus_fail(ctx, ARGUS_ESHAPE, "batch half width %d not in 4..10", spec->half_width);
     if (n_cutouts < 1 || !cutouts || n_frames < 1 || !frame_widths || !frame_heights)
@@ -562,7 +566,7 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *b, const argus_frame *frames, f
             float best = 1e30f;
             for (int cand = 0; cand < N_CAND; ++cand) {
                 ARGUS_HIP_CHECK(ctx, hipEventRecord(e0, b->stream));
-                int rc = batch_launch(ctx, ba, b->h, cand, b->stream);
+                int rc = batch_launch(ctx, ba, b->h, b->spec.precision, cand, b->stream);
                 if (rc) return rc;
                 ARGUS_HIP_CHECK(ctx, hipEventRecord(e1, b->stream));
                 ARGUS_HIP_CHECK(ctx, hipEventSynchronize(e1));
@@ -578,7 +582,7 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *b, const argus_frame *frames, f
         if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
         if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
         ARGUS_HIP_CHECK(ctx, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        int rc = batch_launch(ctx, ba, b->h, b->choice, b->stream);
+        int rc = batch_launch(ctx, ba, b->h, b->spec.precision, b->choice, b->stream);
         hipGraph_t g = nullptr;
         hipError_t ec = hipStreamEndCapture(b->stream, &g);
         if (rc) return rc;

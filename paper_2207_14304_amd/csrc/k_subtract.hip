@@ -21,7 +21,7 @@ struct SubArgs {
     const uint8_t *rmask, *smask;
     float *diff, *dvar;
     uint8_t *dmask;
-    double *partials;          // [n_blocks][2]: chi^2, count
+    double *partials;          // [n_blocks][4]: chi^2, count, sum w D, sum w
     int64_t pitch;
     int W, H, D, Dbg;
     int RX, RY, bpx, bpy;      // regions and blocks per region
@@ -49,8 +49,7 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
     float *St = Vt + TH * TW;                           // [NS][K*K]
     uint8_t *Mt = (uint8_t *)(St + NS * K * K);         // [TH][MW] ref mask != 0
     uint8_t *Mr = Mt + TH * MW;                         // [TH][BW] row-OR over 2h+1
-    __shared__ double red_c[NTHR / 64];
-    __shared__ double red_n[NTHR / 64];
+    __shared__ double red[4][NTHR / 64];
 
     const int tid = threadIdx.x;
     const int bid = blockIdx.x;
@@ -64,7 +63,7 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
     const int bx1 = min(bx0 + BW, rx1), by1 = min(by0 + BH, ry1);
     const int64_t P = a.pitch;
 
-    double c2 = 0.0, cnt = 0.0;
+    double c2 = 0.0, cnt = 0.0, swd = 0.0, sw = 0.0;
     if (bx0 < bx1 && by0 < by1) {
         // halo tiles of the reference, its variance and mask
         for (int i = tid; i < TH * L::TWr; i += NTHR) {
@@ -188,8 +187,11 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
                         outv[i] = sv + v[i];
                         const float tot = sv + a.rvar[o];
                         if (tot > 0.f) {
-                            c2 += (double)dval * (double)dval / (double)tot;
+                            const double w = 1.0 / (double)tot, wd = w * (double)dval;
+                            c2 += wd * (double)dval;
                             cnt += 1.0;
+                            swd += wd;
+                            sw += w;
                         }
                     }
                 }
@@ -217,41 +219,52 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
             }
         }
     }
-    // fixed-order block reduction of chi^2 and the fit-set count
+    // fixed-order block reduction of chi^2, the fit-set count, sum w D, sum w
     for (int off = 32; off > 0; off >>= 1) {
         c2 += __shfl_xor(c2, off);
         cnt += __shfl_xor(cnt, off);
+        swd += __shfl_xor(swd, off);
+        sw += __shfl_xor(sw, off);
     }
-    if ((tid & 63) == 0) { red_c[tid >> 6] = c2; red_n[tid >> 6] = cnt; }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = c2; red[1][tid >> 6] = cnt; red[2][tid >> 6] = swd; red[3][tid >> 6] = sw;
+    }
     __syncthreads();
-    if (tid == 0) {
-        double sc = 0.0, sn = 0.0;
-        for (int i = 0; i < NTHR / 64; ++i) { sc += red_c[i]; sn += red_n[i]; }
-        a.partials[2 * (size_t)bid] = sc;
-        a.partials[2 * (size_t)bid + 1] = sn;
+    if (tid < 4) {
+        double sc = 0.0;
+        for (int i = 0; i < NTHR / 64; ++i) sc += red[tid][i];
+        a.partials[4 * (size_t)bid + tid] = sc;
     }
 }
 
-// One workgroup per solve: fixed-order sum of its blocks' partials.
-__global__ void chi2_reduce_kernel(const double *part, int per_solve, double *chi2, int64_t *n) {
-    __shared__ double rc[4], rn[4];
+// One workgroup (256 threads) per solve: fixed-order sum of its blocks' partials.
+__global__ void chi2_reduce_kernel(const double *part, int per_solve, double *chi2, int64_t *n,
+                                   double *sum_wd, double *sum_w) {
+    __shared__ double rs[4][4];
     const int s = blockIdx.x, tid = threadIdx.x;
-    double c = 0.0, k = 0.0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = tid; j < per_solve; j += blockDim.x) {
-        c += part[2 * ((size_t)s * per_solve + j)];
-        k += part[2 * ((size_t)s * per_solve + j) + 1];
+        const double *q = part + 4 * ((size_t)s * per_solve + j);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] += q[c];
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        c += __shfl_xor(c, off);
-        k += __shfl_xor(k, off);
-    }
-    if ((tid & 63) == 0) { rc[tid >> 6] = c; rn[tid >> 6] = k; }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rs[c][tid >> 6] = v[c];
     __syncthreads();
     if (tid == 0) {
-        double sc = 0.0, sn = 0.0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { sc += rc[i]; sn += rn[i]; }
-        if (chi2) chi2[s] = sc;
-        if (n) n[s] = (int64_t)sn;
+        double t[4];
+        for (int c = 0; c < 4; ++c) {
+            t[c] = 0.0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t[c] += rs[c][i];
+        }
+        if (chi2) chi2[s] = t[0];
+        if (n) n[s] = (int64_t)t[1];
+        if (sum_wd) sum_wd[s] = t[2];
+        if (sum_w) sum_w[s] = t[3];
     }
 }
 
@@ -289,7 +302,8 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                     const float *stamps, const float *bg, const float *ref,
                     const float *ref_var, const uint8_t *ref_mask, const float *sci,
                     const float *sci_var, const uint8_t *sci_mask, float *diff, float *diff_var,
-                    uint8_t *diff_mask, double *chi2, int64_t *n_chi2) {
+                    uint8_t *diff_mask, double *chi2, int64_t *n_chi2, double *sum_wd,
+                    double *sum_w) {
     SubArgs a;
     a.stamps = stamps; a.bg = bg; a.ref = ref; a.rvar = ref_var; a.sci = sci; a.svar = sci_var;
     a.rmask = ref_mask; a.smask = sci_mask; a.diff = diff; a.dvar = diff_var; a.dmask = diff_mask;
@@ -306,7 +320,7 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
     const int n_solves = a.RX * a.RY;
     const int per_solve = a.bpx * a.bpy;
     const int n_blocks = n_solves * per_solve;
-    int rc = argus_ws_reserve(ctx, (size_t)n_blocks * 2 * sizeof(double) + 256);
+    int rc = argus_ws_reserve(ctx, (size_t)n_blocks * 4 * sizeof(double) + 256);
     if (rc) return rc;
     a.partials = (double *)ctx->ws;
     argus_time_begin(ctx);
@@ -317,9 +331,9 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
     }
     if (rc) return rc;
     argus_time_end(ctx, "subtract");
-    if (chi2 || n_chi2) {
+    if (chi2 || n_chi2 || sum_wd || sum_w) {
         hipLaunchKernelGGL(chi2_reduce_kernel, dim3(n_solves), dim3(256), 0, ctx->stream,
-                           (const double *)a.partials, per_solve, chi2, n_chi2);
+                           (const double *)a.partials, per_solve, chi2, n_chi2, sum_wd, sum_w);
         ARGUS_HIP_CHECK(ctx, hipGetLastError());
     }
     return ARGUS_OK;

@@ -25,8 +25,10 @@ def _gen(seed, k, device):
     return g
 
 
-def render(W, H, xs, ys, fl, fwhm, device, chunk=2048):
-    """Sum of truncated unit-sum Moffat stars (float32 [H][W], electrons)."""
+def render(W, H, xs, ys, fl, fwhm, device, chunk=2048, ell=0.0, theta=0.0):
+    """Sum of truncated unit-sum Moffat stars (float32 [H][W], electrons).
+    ell > 0 stretches the profile along position angle theta with axis ratio
+    1 - ell at constant area (r^2 = q x'^2 + y'^2 / q, q = 1 - ell)."""
     import torch
     img = torch.zeros(H * W, dtype=torch.float32, device=device)
     R = int(math.ceil(8.0 * fwhm))
@@ -40,7 +42,14 @@ def render(W, H, xs, ys, fl, fwhm, device, chunk=2048):
         yi = torch.round(y).to(torch.int64)
         dx = (xi[:, None] + off[None, :].to(torch.int64)).to(torch.float32) - x[:, None]
         dy = (yi[:, None] + off[None, :].to(torch.int64)).to(torch.float32) - y[:, None]
-        r2 = dy[:, :, None] ** 2 + dx[:, None, :] ** 2
+        if ell > 0.0:
+            q = 1.0 - ell
+            c, sn = math.cos(theta), math.sin(theta)
+            xp = c * dx[:, None, :] + sn * dy[:, :, None]
+            yp = -sn * dx[:, None, :] + c * dy[:, :, None]
+            r2 = q * xp ** 2 + yp ** 2 / q
+        else:
+            r2 = dy[:, :, None] ** 2 + dx[:, None, :] ** 2
         p = (1.0 + r2 / alpha2) ** -3.0
         p = torch.where(r2 <= (8.0 * fwhm) ** 2, p, torch.zeros_like(p))
         p = p * (f / p.sum(dim=(1, 2)))[:, None, None]
@@ -53,8 +62,11 @@ def render(W, H, xs, ys, fl, fwhm, device, chunk=2048):
 
 
 def make_pair(W, H, n_stars, seed, fwhm_sci, ratio=2.0 / 2.6, sky=800.0, scale=1.05,
-              device="cuda"):
-    """Science and reference raw uint16 frames (device) plus star positions."""
+              device="cuda", ell=0.0, theta=0.0, noise_free=False):
+    """Science and reference raw uint16 frames (device) plus star positions.
+    The science PSF may be elliptical (ell, theta).  With noise_free the
+    expected electron images (scene + sky, float32) are returned as two more
+    values."""
     import torch
     g = _gen(seed, 0, device)
     xs = torch.rand(n_stars, generator=g, device=device, dtype=torch.float64) * W
@@ -64,7 +76,7 @@ def make_pair(W, H, n_stars, seed, fwhm_sci, ratio=2.0 / 2.6, sky=800.0, scale=1
     fl = (a + u * (b - a)) ** (-4.0 / 3.0)
     xs32, ys32, fl32 = xs.float(), ys.float(), fl.float()
     ref_scene = render(W, H, xs32, ys32, fl32, fwhm_sci * ratio, device)
-    sci_scene = render(W, H, xs32, ys32, scale * fl32, fwhm_sci, device)
+    sci_scene = render(W, H, xs32, ys32, scale * fl32, fwhm_sci, device, ell=ell, theta=theta)
 
     def expose(scene, k):
         gk = _gen(seed, k, device)
@@ -81,4 +93,7 @@ def make_pair(W, H, n_stars, seed, fwhm_sci, ratio=2.0 / 2.6, sky=800.0, scale=1
         # values are in 0..65535: keep the low 16 bits as uint16
         return (t & 0xFFFF).to(torch.int16).view(torch.uint16)
 
-    return u16(sci), u16(ref), xs.cpu().numpy(), ys.cpu().numpy()
+    out = (u16(sci), u16(ref), xs.cpu().numpy(), ys.cpu().numpy())
+    if noise_free:
+        out += (sci_scene + sky, ref_scene + sky)
+    return out

