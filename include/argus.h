@@ -112,9 +112,13 @@ void argus_ctx_destroy(argus_ctx *ctx);
 int  argus_ctx_set_stream(argus_ctx *ctx, void *hip_stream);
 /* Message of the most recent synchronous failure on this ctx ("" if none). */
 const char *argus_last_error(const argus_ctx *ctx);
-/* Device time in milliseconds of the most recent launch of the named
- * internal kernel, or -1 if timing is off; timing records HIP events around
- * each launch when enabled (for measurement only). */
+/* Per-kernel timing (for measurement only): while enabled, every launch of
+ * an internal kernel is bracketed by HIP events on the context stream, with
+ * no synchronisation.  argus_kernel_time_ms waits for the recorded launches
+ * of the named kernel ("calibrate", "coadd", "fit_accum", "fit_reduce",
+ * "fit_solve", "subtract", "detect_map", "batch") and returns their average device
+ * time in ms, or -1 if none was recorded.  Enabling or disabling timing
+ * discards the records. */
 int  argus_ctx_set_timing(argus_ctx *ctx, int enable);
 float argus_kernel_time_ms(argus_ctx *ctx, const char *kernel);
 
@@ -315,7 +319,9 @@ int  argus_surrogate_select(argus_ctx *ctx, int n_solves, int n_basis, const dou
 /* Surrogate inputs of a tiled frame pair: per tile (raster order) the
  * positive reference local maxima (strictly above earlier 8-neighbours in
  * raster order, >= later ones) whose (2 half + 1)^2 stamp lies in the frame
- * are ranked brightest first (raster order on ties); walking down the
+ * and whose peak is >= snr_min sigmas above the tile's sky (the FP32 median
+ * of its unmasked reference pixels, by radix select) are ranked brightest
+ * first (raster order on ties); walking down the
  * ranking, a candidate is kept when its stamp is unmasked in both frames and
  * (peak - border median of its reference stamp) / sqrt(ref_var at the peak)
  * >= snr_min (FP32), until stamps_per_tile are kept.  Each kept pair loses

@@ -36,13 +36,15 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
 
     Candidates are positive reference local maxima (strictly above the
     8-neighbours earlier in raster order, >= the later ones) whose
-    (2r+1)^2 stamp lies inside the frame, ranked brightest first with raster
+    (2r+1)^2 stamp lies inside the frame and whose peak stands snr_min noise
+    sigmas above the tile's sky, the median of its unmasked reference pixels
+    (no candidates when all are masked), ranked brightest first with raster
     order breaking ties.  Walking down the ranking a candidate is kept when
     its stamp is unmasked in both frames and (peak - border median of its
     reference stamp) / sqrt(var at the peak) >= snr_min; the walk stops at S.
-    That test decides an integer (which stamps are kept), so it is taken in
-    float32, the precision of the frames: the median averages the middle
-    pair in float32, and the division and square root round correctly."""
+    Both tests decide integers (which stamps are kept), so they are taken in
+    float32, the precision of the frames: medians average the middle pair in
+    float32, and the division and square root round correctly."""
     ref = np.asarray(ref, np.float64)
     r32 = np.asarray(ref, np.float32)
     v32 = np.asarray(ref_var, np.float32)
@@ -61,11 +63,20 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
     out = []
     for (y0, y1) in core.tile_bounds(H, tiles_y):
         for (x0, x1) in core.tile_bounds(W, tiles_x):
+            un = r32[y0:y1, x0:x1][np.asarray(ref_mask)[y0:y1, x0:x1] == 0]
+            if un.size == 0:
+                out.append([])
+                continue
+            sky = median32(un)
             ys, xs = np.nonzero(lm[y0:y1, x0:x1])
             ys, xs = ys + y0, xs + x0
             inside = (ys >= r) & (xs >= r) & (ys < H - r) & (xs < W - r)
-            cand = sorted(zip(ys[inside], xs[inside]), key=lambda p: (-ref[p[0], p[1]],
-                                                                       p[0] * W + p[1]))
+            ys, xs = ys[inside], xs[inside]
+            with np.errstate(all="ignore"):
+                vv = v32[ys, xs]
+                above = (vv > 0) & ((r32[ys, xs] - sky) / np.sqrt(vv) >= np.float32(snr_min))
+            cand = sorted(zip(ys[above], xs[above]), key=lambda p: (-ref[p[0], p[1]],
+                                                                     p[0] * W + p[1]))
             keep = []
             for y, x in cand:
                 if len(keep) == S:
@@ -82,13 +93,18 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
     return out
 
 
-def border_median32(st):
-    """Median of a stamp's border in float32 (middle pair averaged in float32)."""
-    b = np.sort(np.concatenate([st[0, :], st[-1, :], st[1:-1, 0], st[1:-1, -1]]).astype(np.float32))
+def median32(v):
+    """Median in float32: the middle value, or the middle pair averaged in float32."""
+    b = np.sort(np.asarray(v, np.float32).ravel())
     k = b.size
     if k % 2:
         return b[k // 2]
     return (b[k // 2 - 1] + b[k // 2]) * np.float32(0.5)
+
+
+def border_median32(st):
+    """Median of a stamp's border in float32."""
+    return median32(np.concatenate([st[0, :], st[-1, :], st[1:-1, 0], st[1:-1, -1]]))
 
 
 def border_median(st):

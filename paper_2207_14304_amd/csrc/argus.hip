@@ -44,19 +44,40 @@ int argus_ws_reserve(argus_ctx *ctx, size_t bytes) {
     return ARGUS_OK;
 }
 
-void argus_time_begin(argus_ctx *ctx) {
-    if (ctx->timing) (void)hipEventRecord(ctx->ev0, ctx->stream);
+static hipEvent_t pool_event(argus_ctx *ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
 }
 
-void argus_time_end(argus_ctx *ctx, const char *name) {
+static void release_times(argus_ctx *ctx) {
+    for (auto &t : ctx->times) {
+        ctx->ev_pool.push_back(t.b);
+        ctx->ev_pool.push_back(t.e);
+    }
+    ctx->times.clear();
+    if (ctx->ev_open) ctx->ev_pool.push_back(ctx->ev_open);
+    ctx->ev_open = nullptr;
+}
+
+void argus_time_begin(argus_ctx *ctx) {
     if (!ctx->timing) return;
-    (void)hipEventRecord(ctx->ev1, ctx->stream);
-    (void)hipEventSynchronize(ctx->ev1);
-    float ms = -1.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    for (int i = 0; i < ctx->n_times; ++i)
-        if (ctx->times[i].name == name) { ctx->times[i].ms = ms; return; }
-    if (ctx->n_times < 16) ctx->times[ctx->n_times++] = {name, ms};
+    if (!ctx->ev_open) ctx->ev_open = pool_event(ctx);
+    if (ctx->ev_open) (void)hipEventRecord(ctx->ev_open, ctx->stream);
+}
+
+// name: a string literal (kept by pointer)
+void argus_time_end(argus_ctx *ctx, const char *name) {
+    if (!ctx->timing || !ctx->ev_open) return;
+    hipEvent_t e = pool_event(ctx);
+    if (!e) return;
+    (void)hipEventRecord(e, ctx->stream);
+    ctx->times.push_back({name, ctx->ev_open, e});
+    ctx->ev_open = nullptr;
 }
 
 extern "C" {
@@ -73,11 +94,6 @@ int argus_ctx_create(int device, argus_ctx **out) {
         delete c;
         return ARGUS_ENOMEM;
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        (void)hipFree(c->tables);
-        delete c;
-        return ARGUS_EHIP;
-    }
     *out = c;
     return ARGUS_OK;
 }
@@ -88,8 +104,8 @@ void argus_ctx_destroy(argus_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->tables) (void)hipFree(ctx->tables);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    release_times(ctx);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -105,15 +121,24 @@ const char *argus_last_error(const argus_ctx *ctx) { return ctx ? ctx->err.c_str
 int argus_ctx_set_timing(argus_ctx *ctx, int enable) {
     if (!ctx) return ARGUS_EINVAL;
     ctx->timing = enable != 0;
-    ctx->n_times = 0;
+    release_times(ctx);
     return ARGUS_OK;
 }
 
 float argus_kernel_time_ms(argus_ctx *ctx, const char *kernel) {
     if (!ctx || !kernel) return -1.f;
-    for (int i = 0; i < ctx->n_times; ++i)
-        if (ctx->times[i].name == kernel) return ctx->times[i].ms;
-    return -1.f;
+    double sum = 0.0;
+    int n = 0;
+    for (auto &t : ctx->times) {
+        if (strcmp(t.name, kernel) != 0) continue;
+        float ms = -1.f;
+        if (hipEventSynchronize(t.e) != hipSuccess ||
+            hipEventElapsedTime(&ms, t.b, t.e) != hipSuccess)
+            return -1.f;
+        sum += ms;
+        ++n;
+    }
+    return n ? (float)(sum / n) : -1.f;
 }
 
 static int check_dims(argus_ctx *ctx, argus_dims d) {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "argus.h"
 
@@ -41,13 +42,13 @@ struct argus_ctx {
     BasisTables *tables = nullptr;
     bool tables_valid = false;
     argus_kernel_spec tables_spec{};
-    // optional per-kernel timing
+    // optional per-kernel timing: an event pair per timed launch, read back
+    // (and averaged per kernel name) only when queried
     bool timing = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::string last_kernel;
-    struct Timed { std::string name; float ms; };
-    Timed times[16];
-    int n_times = 0;
+    struct Timed { const char *name; hipEvent_t b, e; };
+    std::vector<Timed> times;
+    std::vector<hipEvent_t> ev_pool;
+    hipEvent_t ev_open = nullptr;
 };
 
 // ---- helpers implemented in argus.hip --------------------------------------

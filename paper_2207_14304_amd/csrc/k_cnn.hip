@@ -351,8 +351,9 @@ __global__ void cnn_pack_kernel(const float *w, int cin, int kp, bf16 *wb, bf16 
 // ---------------------------------------------------------------------------
 // Stamp extraction: one workgroup per tile.  Candidates are positive
 // reference local maxima (strictly above earlier 8-neighbours in raster
-// order, >= later ones) whose stamp lies inside the frame, ranked brightest
-// first (raster order on ties).  Walking down the ranking, a candidate is
+// order, >= later ones) whose stamp lies inside the frame and whose peak
+// stands snr_min noise sigmas above the tile's sky (the median of its
+// unmasked reference pixels), ranked brightest first (raster order on ties).  Walking down the ranking, a candidate is
 // kept when its stamp is unmasked in both frames and its peak stands
 // snr_min noise sigmas above the reference stamp's border median; the walk
 // stops at S kept.  Each kept stamp pair has its border medians removed and
@@ -418,6 +419,48 @@ __device__ float border_median_wave(const float *st, int n, float *buf, int lane
     return med;
 }
 
+// Order-preserving unsigned key of a float (NaN excluded by the caller).
+__device__ __forceinline__ uint32_t fkey(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unkey(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// Key of the rank-k (0-based) unmasked reference value of the tile: radix
+// select over 8-bit digits with a 256-bin LDS histogram per pass.
+__device__ uint32_t tile_select(const StampArgs &a, int x0, int y0, int tw, int npix, int k,
+                                int *bins) {
+    const int tid = threadIdx.x;
+    const int64_t P = a.pitch;
+    uint32_t prefix = 0, pmask = 0;
+    __shared__ int s_digit, s_k;
+    if (tid == 0) s_k = k;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        bins[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < npix; i += NT) {
+            const int64_t o = (int64_t)(y0 + i / tw) * P + x0 + i % tw;
+            if (a.rmask[o] != 0) continue;
+            const uint32_t key = fkey(a.ref[o]);
+            if ((key & pmask) == prefix) atomicAdd(&bins[(key >> shift) & 255u], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int kk = s_k, d = 0;
+            while (d < 255 && kk >= bins[d]) { kk -= bins[d]; ++d; }
+            s_digit = d;
+            s_k = kk;
+        }
+        __syncthreads();
+        prefix |= (uint32_t)s_digit << shift;
+        pmask |= 255u << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
 __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
     __shared__ unsigned long long keys[MAXC];
     __shared__ int hist[NBUCKET];
@@ -434,19 +477,46 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
     const int y0 = (int)((int64_t)ty * a.H / a.TY), y1 = (int)((int64_t)(ty + 1) * a.H / a.TY);
     const int r = a.r, n = 2 * r + 1, npx = n * n;
     const int64_t P = a.pitch;
+    const int tw = x1 - x0, npix = tw * (y1 - y0);
+    // the tile's sky: median of its unmasked reference pixels (middle pair
+    // averaged in FP32); +inf when every pixel is masked (no candidates)
+    __shared__ int s_nun;
+    if (tid == 0) s_nun = 0;
+    __syncthreads();
+    {
+        int cnt = 0;
+        for (int i = tid; i < npix; i += NT)
+            cnt += a.rmask[(int64_t)(y0 + i / tw) * P + x0 + i % tw] == 0;
+        atomicAdd(&s_nun, cnt);
+    }
+    __syncthreads();
+    const int nun = s_nun;
+    float sky = __builtin_inff();
+    if (nun > 0) {
+        const float v1 = unkey(tile_select(a, x0, y0, tw, npix, (nun - 1) / 2, hist));
+        if (nun & 1) {
+            sky = v1;
+        } else {
+            const float v2 = unkey(tile_select(a, x0, y0, tw, npix, nun / 2, hist));
+            sky = (v1 + v2) * 0.5f;
+        }
+    }
     for (int i = tid; i < NBUCKET; i += NT) hist[i] = 0;
     if (tid == 0) { ncand = 0; nacc = 0; }
     __syncthreads();
     // candidate test; the stamp-in-frame bound keeps every neighbour in the frame
     auto is_cand = [&](int y, int x, float &c) -> bool {
         if (y < r || x < r || y >= a.H - r || x >= a.W - r) return false;
-        const float *q = a.ref + (int64_t)y * P + x;
+        const int64_t o = (int64_t)y * P + x;
+        const float *q = a.ref + o;
         c = q[0];
         if (!(c > 0.f)) return false;
-        return c > q[-P - 1] && c > q[-P] && c > q[-P + 1] && c > q[-1] && c >= q[1] &&
-               c >= q[P - 1] && c >= q[P] && c >= q[P + 1];
+        if (!(c > q[-P - 1] && c > q[-P] && c > q[-P + 1] && c > q[-1] && c >= q[1] &&
+              c >= q[P - 1] && c >= q[P] && c >= q[P + 1]))
+            return false;
+        const float vv = a.rvar[o];
+        return vv > 0.f && (c - sky) / sqrtf(vv) >= a.snr_min;
     };
-    const int tw = x1 - x0, npix = tw * (y1 - y0);
     for (int i = tid; i < npix; i += NT) {
         float c;
         if (is_cand(y0 + i / tw, x0 + i % tw, c)) atomicAdd(&hist[__float_as_uint(c) >> 20], 1);

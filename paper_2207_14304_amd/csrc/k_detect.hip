@@ -1,9 +1,10 @@
 // Detection on the difference image: noise-normalised map, threshold,
 // raster-ordered local maxima, stable compaction, PSF-weighted fluxes.
 //
-// detect_map: one workgroup per 1024 x 4 tile.  It forms the SNR of its rows
-//   and one halo row/column on each side in LDS, writes snr and det_mask and
-//   counts the candidates of each 1024-pixel row segment.
+// detect_map: one workgroup per 256 x 16 tile.  It forms the SNR of its rows
+//   and one halo row/column on each side in LDS (4-pixel vector loads), writes
+//   snr and det_mask (4-pixel vector stores) and counts the candidates of
+//   each 256-pixel row segment.
 // scan_tiles / scan_top: exclusive scan of the segment counts (1024-count
 //   tiles in parallel, then the tile totals) -> raster-order offsets.
 // detect_emit: one wave per segment with candidates writes them in raster
@@ -12,8 +13,9 @@
 
 namespace {
 
-constexpr int SEG = 1024, ROWS = 4, NTHR = 256, PXT = SEG / 64;   // 16 px per thread
-constexpr int STILE = 1024;                                        // counts per scan tile
+constexpr int SEG = 256, ROWS = 16, NTHR = 256;   // a wave covers a 256-pixel row, 4 px a lane
+constexpr int LW = SEG + 8;                        // LDS row: [3] = x0-1, [4..259], [260] = x0+256
+constexpr int STILE = 1024;                        // counts per scan tile
 
 struct DetArgs {
     const float *diff, *dvar;
@@ -29,6 +31,7 @@ struct DetArgs {
     int32_t *n_cands;
     int64_t pitch;
     int W, H, nsx, nseg, ntile, r, cap;
+    int vec;                   // 16-byte aligned planes, pitch % 4 == 0
     float thr;
 };
 
@@ -42,39 +45,83 @@ __device__ __forceinline__ float snr_at(const DetArgs &a, int x, int y) {
     return a.diff[o] * __builtin_amdgcn_rsqf(V);
 }
 
+__device__ __forceinline__ float snr_of(float D, float V, uint32_t m) {
+    return (m != 0 || !(V > 0.f)) ? 0.f : D * __builtin_amdgcn_rsqf(V);
+}
+
 __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
-    __shared__ float s[ROWS + 2][SEG + 4];
+    __shared__ __align__(16) float s[ROWS + 2][LW];
     const int sx = blockIdx.x, y0 = blockIdx.y * ROWS, tid = threadIdx.x;
     const int x0 = sx * SEG;
-    for (int i = tid; i < (ROWS + 2) * (SEG + 2); i += NTHR) {
-        int row = i / (SEG + 2), c = i % (SEG + 2);
-        s[row][c] = snr_at(a, x0 - 1 + c, y0 - 1 + row);
+    const int64_t P = a.pitch;
+    // SNR of rows y0-1 .. y0+ROWS, 4-pixel chunks
+    for (int i = tid; i < (ROWS + 2) * (SEG / 4); i += NTHR) {
+        const int row = i / (SEG / 4), ch = i % (SEG / 4);
+        const int y = y0 - 1 + row, x = x0 + 4 * ch;
+        float4 v;
+        if (y < 0 || y >= a.H) {
+            v = make_float4(-__builtin_inff(), -__builtin_inff(), -__builtin_inff(),
+                            -__builtin_inff());
+        } else if (a.vec && x + 3 < a.W) {
+            const int64_t o = (int64_t)y * P + x;
+            const float4 D = *(const float4 *)(a.diff + o);
+            const float4 V = *(const float4 *)(a.dvar + o);
+            const uint32_t m = *(const uint32_t *)(a.dmask + o);
+            v = make_float4(snr_of(D.x, V.x, m & 0xffu), snr_of(D.y, V.y, (m >> 8) & 0xffu),
+                            snr_of(D.z, V.z, (m >> 16) & 0xffu), snr_of(D.w, V.w, m >> 24));
+        } else {
+            v = make_float4(snr_at(a, x, y), snr_at(a, x + 1, y), snr_at(a, x + 2, y),
+                            snr_at(a, x + 3, y));
+        }
+        *(float4 *)&s[row][4 + 4 * ch] = v;
+    }
+    if (tid < 2 * (ROWS + 2)) {
+        const int row = tid >> 1, side = tid & 1;
+        s[row][side ? 4 + SEG : 3] = snr_at(a, side ? x0 + SEG : x0 - 1, y0 - 1 + row);
     }
     __syncthreads();
-    const int rr = tid >> 6, lane = tid & 63;     // wave rr owns tile row rr
-    const int y = y0 + rr;
-    int cnt = 0;
-    if (y < a.H) {
-        // pixel lx = 64 j + lane: consecutive lanes read consecutive LDS words
-        const int64_t orow = (int64_t)y * a.pitch;
-#pragma unroll 4
-        for (int j = 0; j < PXT; ++j) {
-            const int lx = 64 * j + lane, x = x0 + lx;
-            const float c = s[rr + 1][lx + 1];
+    const int lane = tid & 63, w = tid >> 6;
+    const int x = x0 + 4 * lane;
+    for (int k = 0; k < ROWS / 4; ++k) {
+        const int rr = w + 4 * k, y = y0 + rr;
+        if (y >= a.H) break;                       // uniform across the wave
+        float up[6], md[6], dn[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            up[j] = s[rr][3 + 4 * lane + j];
+            md[j] = s[rr + 1][3 + 4 * lane + j];
+            dn[j] = s[rr + 2][3 + 4 * lane + j];
+        }
+        float outs[4];
+        uint32_t outd = 0;
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float c = md[e + 1];
             const bool det = c >= a.thr;
-            bool cand = det && c > s[rr][lx] && c > s[rr][lx + 1] && c > s[rr][lx + 2] &&
-                        c > s[rr + 1][lx];
-            cand = cand && c >= s[rr + 1][lx + 2] && c >= s[rr + 2][lx] &&
-                   c >= s[rr + 2][lx + 1] && c >= s[rr + 2][lx + 2];
-            if (x < a.W) {
-                if (a.snr) a.snr[orow + x] = (c == -__builtin_inff()) ? 0.f : c;
-                a.det[orow + x] = (det ? ARGUS_DET : 0u) | (cand ? ARGUS_CAND : 0u);
-                cnt += cand ? 1 : 0;
+            const bool cand = det && c > up[e] && c > up[e + 1] && c > up[e + 2] && c > md[e] &&
+                              c >= md[e + 2] && c >= dn[e] && c >= dn[e + 1] && c >= dn[e + 2];
+            outs[e] = (c == -__builtin_inff()) ? 0.f : c;
+            const uint32_t dv = (det ? ARGUS_DET : 0u) | (cand ? ARGUS_CAND : 0u);
+            outd |= dv << (8 * e);
+            cnt += (cand && x + e < a.W) ? 1 : 0;
+        }
+        const int64_t o = (int64_t)y * P + x;
+        if (a.vec && x + 3 < a.W) {
+            if (a.snr) *(float4 *)(a.snr + o) = make_float4(outs[0], outs[1], outs[2], outs[3]);
+            *(uint32_t *)(a.det + o) = outd;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (x + e < a.W) {
+                    if (a.snr) a.snr[o + e] = outs[e];
+                    a.det[o + e] = (uint8_t)(outd >> (8 * e));
+                }
             }
         }
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if (lane == 0) a.counts[y * a.nsx + sx] = cnt;
     }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if (lane == 0 && y < a.H) a.counts[y * a.nsx + sx] = cnt;
 }
 
 // Exclusive scan of one tile of STILE segment counts.
@@ -187,6 +234,9 @@ int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *
     a.nseg = a.nsx * d.height;
     a.ntile = (a.nseg + STILE - 1) / STILE;
     a.r = r; a.cap = cap; a.thr = thr;
+    auto al = [](const void *p, uintptr_t m) { return p == nullptr || ((uintptr_t)p % m) == 0; };
+    a.vec = (d.pitch % 4 == 0) && al(diff, 16) && al(dvar, 16) && al(snr, 16) && al(dmask, 4) &&
+            al(det, 4);
     size_t need = ((size_t)2 * a.nseg + 2 * a.ntile + 64) * sizeof(int32_t);
     int rc = argus_ws_reserve(ctx, need);
     if (rc) return rc;

@@ -26,7 +26,7 @@ from .synth import READ_NOISE_E
 TILES = 4
 HALF = 7
 NB = 31
-SNR_MIN = 10.0
+SNR_MIN = 5.0
 
 
 def spec(tiles=TILES, half=HALF):
@@ -142,6 +142,29 @@ def build_training_set(ctx, n_frames, seed, W=1024, H=1024, n_stars=(300, 4000),
     return torch.cat(Xs), torch.cat(Vs), torch.cat(Ts)
 
 
+def standardize(target):
+    """Per-coefficient mean and standard deviation of the training targets and
+    the standardized targets the network is trained on (so that the squared
+    error weighs every coefficient alike)."""
+    mu = target.mean(0)
+    sd = target.std(0).clamp_min(1e-6)
+    return (target - mu) / sd, mu, sd
+
+
+def fold_standardization(flat, mu, sd):
+    """Head weights that output coefficients directly: c = mu + sd (W q + b)."""
+    layout, _ = argus.cnn_param_layout()
+    sw, shw = layout["hw"]
+    sb, _ = layout["hb"]
+    out = np.array(flat, np.float32, copy=True)
+    mu = np.asarray(mu, np.float64)
+    sd = np.asarray(sd, np.float64)
+    hw = out[sw].reshape(shw).astype(np.float64)
+    out[sw] = (sd[:, None] * hw).reshape(-1)
+    out[sb] = mu + sd * out[sb].astype(np.float64)
+    return out
+
+
 def train(cnn: argus.CNN, X, valid, target, epochs, batch, lr, seed=0, log=None):
     """Minibatch Adam on the GPU; returns the per-step loss history (host)."""
     import torch
@@ -239,3 +262,47 @@ def kernel_error(coeffs, truth, B):
     Kt = np.tensordot(np.asarray(truth)[:, :NB], B, 1)
     return np.linalg.norm((K - Kt).reshape(len(K), -1), axis=1) / \
         np.linalg.norm(Kt.reshape(len(K), -1), axis=1)
+
+
+def basis_stamps(ctx, half=HALF):
+    """The normalised basis B[k][v][u] as the library expands it (host array)."""
+    import torch
+    sp = argus.make_spec(half_width=half, tiles_x=NB, tiles_y=1, mode=argus.FIT_PER_TILE)
+    K = 2 * half + 1
+    co = torch.zeros((NB, NB + 1), dtype=torch.float64, device="cuda")
+    co[:, :NB] = torch.eye(NB, dtype=torch.float64, device="cuda")
+    st = torch.empty((NB, 1, K, K), dtype=torch.float32, device="cuda")
+    bg = torch.empty((NB, 1), dtype=torch.float32, device="cuda")
+    ctx.expand_kernel(sp, co, st, bg)
+    return st[:, 0].double().cpu().numpy()
+
+
+def evaluate(ctx, path: "SurrogatePath", frames, B):
+    """Per tile of every frame: kernel errors of the plain fit and of the
+    network against the fit on the noise-free frames, the acceptance, and the
+    chi^2/dof of the plain fit and of the final (accepted or fallback) kernel."""
+    import torch
+    sp = path.sp
+    rows = []
+    c2 = torch.empty(path.ns, dtype=torch.float64, device="cuda")
+    n2 = torch.empty(path.ns, dtype=torch.int64, device="cuda")
+    for fr in frames:
+        plain = TileFits(ctx, fr.planes, sp)
+        truth = TileFits(ctx, fr.clean, sp, want_chi2=False)
+        path.predict(fr.planes)
+        path.select(plain)
+        path.subtract_final(fr.planes, c2, n2)
+        co_p = plain.coeffs.cpu().numpy()
+        co_s = path.sco.cpu().numpy()
+        co_t = truth.coeffs.cpu().numpy()
+        e_p = kernel_error(co_p, co_t, B)
+        e_s = kernel_error(co_s, co_t, B)
+        rp = (plain.chi2 / (plain.n_chi2 - (NB + 1))).cpu().numpy()
+        rf = (c2 / n2.clamp_min(1)).cpu().numpy()
+        acc = path.accepted.cpu().numpy()
+        st = plain.status.cpu().numpy()
+        for t in range(path.ns):
+            rows.append(dict(err_plain=float(e_p[t]), err_sur=float(e_s[t]),
+                             accepted=int(acc[t]), chi2dof_plain=float(rp[t]),
+                             chi2dof_final=float(rf[t]), status=int(st[t])))
+    return rows

@@ -163,6 +163,19 @@ def test_stamp_snr_is_above_the_border_median():
     assert cs == [[(20, 20), (12, 45)]]
     neg = -ref
     assert sg.select_stamps(neg, var, z, z, 1, 1, r=5, S=8, snr_min=1.0) == [[]]
+    # a peak 10 sigma above its dark surroundings but below the tile's sky
+    # (the median of the unmasked tile) is not a candidate
+    low = ref.copy()
+    low[25:45, 5:25] = 500.0
+    low[35, 15] = 600.0
+    assert sg.select_stamps(low, var, z, z, 1, 1, r=5, S=8, snr_min=10.0) == [[(20, 20), (12, 45)]]
+    # masked pixels do not enter the sky: with only the dark region unmasked
+    # the sky is 500 and its peak (whose stamp lies in that region) is kept
+    m = np.ones((H, W), np.uint8)
+    m[25:45, 5:25] = 0
+    got = sg.select_stamps(low, var, m, z, 1, 1, r=5, S=8, snr_min=10.0)
+    assert got == [[(35, 15)]]
+    assert sg.median32(np.array([1.0, 4.0, 2.0, 3.0], np.float32)) == np.float32(2.5)
     st = np.arange(36.0).reshape(6, 6)
     b = np.r_[st[0], st[-1], st[1:-1, 0], st[1:-1, -1]]
     assert sg.border_median32(st) == np.float32(np.median(b))
