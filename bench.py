@@ -42,7 +42,29 @@ def parse():
     p.add_argument("--batch-frames", type=int, default=20)
     p.add_argument("--batch-cutouts", type=int, default=4000)
     p.add_argument("--batch-steps", type=int, default=3)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="only run a plain 1 GiB device copy (5 times), the reference for "
+                        "scaling hardware byte counters")
     return p.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of 1 GiB, five times: reads and writes
+    exactly 2^30 bytes each, so FETCH_SIZE / WRITE_SIZE counters of these
+    dispatches give the scale from counter units to bytes."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"copy_bytes": 1 << 30, "ms": round(ms, 4),
+                      "GB/s_read+write": round(2 * (1 << 30) / ms / 1e6, 1)}), flush=True)
 
 
 def log(*a):
@@ -172,6 +194,9 @@ def batch_leg(args, torch, argus, synth):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -262,9 +287,25 @@ def main():
         cpu = cpu_baseline(fp, args.cpu_crop, spec_o)
         log("cpu baseline: " + json.dumps(cpu))
 
+    # per-frame difference with the reference resident (calibrate the science
+    # frame, fit, expand, subtract, detect): the per-frame cost once the
+    # reference of a pointing is built
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    for _ in range(args.steps):
+        pipe.difference(sci)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    ms_frame = f0.elapsed_time(f1) / args.steps
+    log(f"per-frame difference: {ms_frame:.3f} ms")
+
     del refs, sci, pipe
     torch.cuda.empty_cache()
-    variants = {}
+    variants = {"per_frame_difference": {
+        "value": round(npix / (ms_frame / 1e3) / 1e6, 2), "unit": "Mpix/s",
+        "ms": round(ms_frame, 4),
+        "workload": "science calibrate + fit + expand + subtract + detect, reference resident"}}
     if args.batch_frames > 0:
         variants["batch"] = batch_leg(args, torch, argus, synth)
 

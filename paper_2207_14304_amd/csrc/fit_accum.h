@@ -15,6 +15,8 @@
 //                A B ~ Ahi Bhi + Ahi Blo + Alo Bhi on v_mfma_f32_16x16x32_bf16
 //                with FP32 accumulation (Henry, Tang & Heinecke 2019).
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -97,19 +99,32 @@ struct WaveGram {
                 floatx4 acc[NTW];
 #pragma unroll
                 for (int j = 0; j < NTW; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-                for (int s = 0; s < SW / 4; ++s) {
+                // operands of step s+1 are loaded while the MFMAs of step s run
+                float nz, n0, n1, nw[NTW];
+                auto load = [&](int s) {
                     const int p = 4 * s + pk;
-                    const float cz = cvec[p * CST];
-                    const float c0 = cvec[p * CST + col] + g0 * cz;
-                    const float c1 = cvec[p * CST + 16 + col] + g1 * cz;
+                    nz = cvec[p * CST];
+                    n0 = cvec[p * CST + col];
+                    n1 = cvec[p * CST + 16 + col];
+#pragma unroll
+                    for (int j = 0; j < NTW; ++j) nw[j] = wx[((WAVE + 4 * j) / 3) * SW + p];
+                };
+                load(0);
+#pragma unroll
+                for (int s = 0; s < SW / 4; ++s) {
+                    const float cz = nz, r0 = n0, r1 = n1;
+                    float wa[NTW];
+#pragma unroll
+                    for (int j = 0; j < NTW; ++j) wa[j] = nw[j];
+                    if (s + 1 < SW / 4) load(s + 1);
+                    const float c0 = r0 + g0 * cz;
+                    const float c1 = r1 + g1 * cz;
 #pragma unroll
                     for (int j = 0; j < NTW; ++j) {
                         const int t = WAVE + 4 * j;
-                        const int a = t / 3, bp = t % 3;
-                        const float wa = wx[a * SW + p];
+                        const int bp = t % 3;
                         const float A = (bp == 2) ? c1 : c0;
-                        const float B = wa * ((bp == 0) ? c0 : c1);
+                        const float B = wa[j] * ((bp == 0) ? c0 : c1);
                         acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, B, acc[j], 0, 0, 0);
                     }
                 }
@@ -118,19 +133,32 @@ struct WaveGram {
                 doublex4 acc[NTW];
 #pragma unroll
                 for (int j = 0; j < NTW; ++j) acc[j] = doublex4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-                for (int s = 0; s < SW / 4; ++s) {
+                float nz, n0, n1;
+                double nw[NTW];
+                auto load = [&](int s) {
                     const int p = 4 * s + pk;
-                    const double cz = (double)cvec[p * CST];
-                    const double c0 = (double)cvec[p * CST + col] + (double)g0 * cz;
-                    const double c1 = (double)cvec[p * CST + 16 + col] + (double)g1 * cz;
+                    nz = cvec[p * CST];
+                    n0 = cvec[p * CST + col];
+                    n1 = cvec[p * CST + 16 + col];
+#pragma unroll
+                    for (int j = 0; j < NTW; ++j) nw[j] = wxd[((WAVE + 4 * j) / 3) * SW + p];
+                };
+                load(0);
+#pragma unroll
+                for (int s = 0; s < SW / 4; ++s) {
+                    const double cz = (double)nz;
+                    const double c0 = (double)n0 + (double)g0 * cz;
+                    const double c1 = (double)n1 + (double)g1 * cz;
+                    double wa[NTW];
+#pragma unroll
+                    for (int j = 0; j < NTW; ++j) wa[j] = nw[j];
+                    if (s + 1 < SW / 4) load(s + 1);
 #pragma unroll
                     for (int j = 0; j < NTW; ++j) {
                         const int t = WAVE + 4 * j;
-                        const int a = t / 3, bp = t % 3;
-                        const double wa = wxd[a * SW + p];
+                        const int bp = t % 3;
                         const double A = (bp == 2) ? c1 : c0;
-                        const double B = wa * ((bp == 0) ? c0 : c1);
+                        const double B = wa[j] * ((bp == 0) ? c0 : c1);
                         acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B, acc[j], 0, 0, 0);
                     }
                 }
@@ -165,6 +193,140 @@ struct WaveGram {
                         for (int e = 0; e < 8; ++e) {
                             const int p = 32 * s + 8 * pk + e;
                             const float B = wx[a * SW + p] * ((bp == 0) ? c0[e] : c1[e]);
+                            const __bf16 bb = (__bf16)B;
+                            bh[e] = bb;
+                            bl[e] = (__bf16)(B - (float)bb);
+                        }
+                        const bf16x8 ah = (bp == 2) ? h1 : h0;
+                        const bf16x8 al = (bp == 2) ? l1 : l0;
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
+                    }
+                }
+                flush(acc, ypw);
+            }
+        }
+    }
+
+    // The same row on k-major operand tables: c[k][p] with row stride CKM
+    // and w xt^a [a][p]; at step s the four lane groups pk take the pixels
+    // p = 16 pk + s (FP32, FP64) or p = 32 s + 8 pk + e (BF16X3), so a lane's
+    // operands of consecutive steps are contiguous and load 16 bytes at once.
+    static constexpr int CKM = SW + 4;
+    __device__ void row_km(const float *cvec, const float *wx, const double *wxd,
+                           const double *ypw, int lane, float g0, float g1) {
+        if constexpr (NTW > 0) {
+            const int col = lane & 15, pk = lane >> 4;
+            if constexpr (PREC == ARGUS_FP32 || PREC == ARGUS_FP64) {
+                using T = typename std::conditional<PREC == ARGUS_FP32, float, double>::type;
+                using TV = typename std::conditional<PREC == ARGUS_FP32, floatx4, doublex4>::type;
+                const float *pa = cvec + col * CKM + 16 * pk;
+                const float *pb = cvec + (16 + col) * CKM + 16 * pk;
+                const float *pz = cvec + 16 * pk;
+                TV acc[NTW];
+#pragma unroll
+                for (int j = 0; j < NTW; ++j) acc[j] = TV{0, 0, 0, 0};
+                // the operands of 4 steps are loaded while the 4 steps before run
+                float4 na, nb, nz;
+                T nw[NTW][4];
+                // (FP64: the weights are read in their own group, as two
+                // groups of FP64 weights do not fit the register budget)
+                auto load = [&](int u) {
+                    na = *(const float4 *)(pa + 4 * u);
+                    nb = *(const float4 *)(pb + 4 * u);
+                    nz = *(const float4 *)(pz + 4 * u);
+                    if constexpr (PREC == ARGUS_FP32) {
+#pragma unroll
+                        for (int j = 0; j < NTW; ++j) {
+                            const int a = (WAVE + 4 * j) / 3;
+                            const float4 w = *(const float4 *)(wx + a * SW + 16 * pk + 4 * u);
+                            nw[j][0] = w.x; nw[j][1] = w.y; nw[j][2] = w.z; nw[j][3] = w.w;
+                        }
+                    }
+                };
+                load(0);
+                // FP64: no unrolling across groups (its accumulators and FP64
+                // sums leave no room for a second group's operands)
+#pragma unroll (PREC == ARGUS_FP32 ? 4 : 1)
+                for (int u = 0; u < 4; ++u) {
+                    const float ca[4] = {na.x, na.y, na.z, na.w};
+                    const float cb[4] = {nb.x, nb.y, nb.z, nb.w};
+                    const float cz[4] = {nz.x, nz.y, nz.z, nz.w};
+                    T w[NTW][4];
+                    if constexpr (PREC == ARGUS_FP32) {
+#pragma unroll
+                        for (int j = 0; j < NTW; ++j)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) w[j][e] = nw[j][e];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < NTW; ++j) {
+                            const int a = (WAVE + 4 * j) / 3;
+                            const double2 w0 = *(const double2 *)(wxd + a * SW + 16 * pk + 4 * u);
+                            const double2 w1 = *(const double2 *)(wxd + a * SW + 16 * pk + 4 * u + 2);
+                            w[j][0] = w0.x; w[j][1] = w0.y; w[j][2] = w1.x; w[j][3] = w1.y;
+                        }
+                    }
+                    if (u + 1 < 4) load(u + 1);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const T c0 = (T)ca[e] + (T)g0 * (T)cz[e];
+                        const T c1 = (T)cb[e] + (T)g1 * (T)cz[e];
+#pragma unroll
+                        for (int j = 0; j < NTW; ++j) {
+                            const int bp = (WAVE + 4 * j) % 3;
+                            const T A = (bp == 2) ? c1 : c0;
+                            const T B = w[j][e] * ((bp == 0) ? c0 : c1);
+                            if constexpr (PREC == ARGUS_FP32)
+                                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, B, acc[j], 0, 0, 0);
+                            else
+                                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B, acc[j], 0, 0, 0);
+                        }
+                    }
+                }
+                flush(acc, ypw);
+            } else {
+                floatx4 acc[NTW];
+#pragma unroll
+                for (int j = 0; j < NTW; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < SW / 32; ++s) {
+                    const int p0 = 32 * s + 8 * pk;          // this lane's 8 pixels
+                    float c0[8], c1[8];
+                    bf16x8 h0, l0, h1, l1;
+                    {
+                        const float4 a0 = *(const float4 *)(cvec + col * CKM + p0);
+                        const float4 a1 = *(const float4 *)(cvec + col * CKM + p0 + 4);
+                        const float4 b0 = *(const float4 *)(cvec + (16 + col) * CKM + p0);
+                        const float4 b1 = *(const float4 *)(cvec + (16 + col) * CKM + p0 + 4);
+                        const float4 z0 = *(const float4 *)(cvec + p0);
+                        const float4 z1 = *(const float4 *)(cvec + p0 + 4);
+                        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+                        const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                        const float zv[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            c0[e] = av[e] + g0 * zv[e];
+                            c1[e] = bv[e] + g1 * zv[e];
+                            const __bf16 x0 = (__bf16)c0[e], x1 = (__bf16)c1[e];
+                            h0[e] = x0;
+                            l0[e] = (__bf16)(c0[e] - (float)x0);
+                            h1[e] = x1;
+                            l1[e] = (__bf16)(c1[e] - (float)x1);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NTW; ++j) {
+                        const int t = WAVE + 4 * j;
+                        const int a = t / 3, bp = t % 3;
+                        const float4 w0 = *(const float4 *)(wx + a * SW + p0);
+                        const float4 w1 = *(const float4 *)(wx + a * SW + p0 + 4);
+                        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+                        bf16x8 bh, bl;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const float B = wv[e] * ((bp == 0) ? c0[e] : c1[e]);
                             const __bf16 bb = (__bf16)B;
                             bh[e] = bb;
                             bl[e] = (__bf16)(B - (float)bb);

@@ -1,6 +1,6 @@
 // Moment accumulation instantiated for ARGUS_FP64.
-#include "fit_accum.h"
+#include "fit_accum8.h"
 
 int fit_accum_launch_fp64(argus_ctx *ctx, const argus_fit::FitArgs &fa, int D, dim3 grid) {
-    return argus_fit::fit_accum_launch<ARGUS_FP64>(ctx, fa, D, grid);
+    return argus_fit::fit_accum8_launch<ARGUS_FP64>(ctx, fa, D, grid);
 }

@@ -20,13 +20,13 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import argus, synth_torch
+from . import argus, synth, synth_torch
 from .synth import READ_NOISE_E
 
 TILES = 4
 HALF = 7
 NB = 31
-SNR_MIN = 5.0
+SNR_MIN = 30.0
 
 
 def spec(tiles=TILES, half=HALF):
@@ -61,6 +61,7 @@ class Frame:
 
     def __init__(self, ctx, W, H, n_stars, seed, cond: Conditions, noise_free=False):
         import torch
+        self.cond = cond
         out = synth_torch.make_pair(W, H, n_stars, seed, cond.fwhm_sci,
                                     ratio=cond.fwhm_ref / cond.fwhm_sci, sky=cond.sky,
                                     scale=cond.scale, ell=cond.ell, theta=cond.theta,
@@ -121,10 +122,15 @@ def extract(ctx, frame_planes, tiles=TILES, snr_min=SNR_MIN):
     return X, valid, ovf
 
 
-def build_training_set(ctx, n_frames, seed, W=1024, H=1024, n_stars=(300, 4000), tiles=TILES):
+def build_training_set(ctx, n_frames, seed, W=1024, H=1024, n_stars=(300, 4000), tiles=TILES,
+                       noise_free_targets=True):
     """Samples (X bf16 [N][64][961][2], valid u8 [N][64], target f32 [N][31]) from
-    n_frames seeded frame pairs: the targets are the plain per-tile fit's kernel
-    coefficients; tiles whose fit failed or that have no valid stamp are dropped."""
+    n_frames seeded frame pairs.  The inputs are stamps of the noisy frames; the
+    targets are the plain per-tile fit's kernel coefficients, by default of the
+    noise-free rendering of the same frames (the fit on noisy frames is biased
+    low in amplitude by the reference's noise and scatters from tile to tile,
+    so it is a poor target), else of the noisy frames themselves.  Tiles whose
+    fit failed or that have no valid stamp are dropped."""
     import torch
     rng = np.random.default_rng(seed)
     sp = spec(tiles)
@@ -132,8 +138,8 @@ def build_training_set(ctx, n_frames, seed, W=1024, H=1024, n_stars=(300, 4000),
     for f in range(n_frames):
         cond = draw_conditions(rng)
         ns = int(rng.integers(n_stars[0], n_stars[1] + 1))
-        fr = Frame(ctx, W, H, ns, int(seed * 100003 + f), cond)
-        fits = TileFits(ctx, fr.planes, sp, want_chi2=False)
+        fr = Frame(ctx, W, H, ns, int(seed * 100003 + f), cond, noise_free=noise_free_targets)
+        fits = TileFits(ctx, fr.clean if noise_free_targets else fr.planes, sp, want_chi2=False)
         X, valid, _ = extract(ctx, fr.planes, tiles)
         keep = (fits.status == 0) & (valid.sum(1) > 0)
         Xs.append(X[keep])
@@ -256,10 +262,16 @@ class SurrogatePath:
                           chi2, n_chi2)
 
 
-def kernel_error(coeffs, truth, B):
-    """||K - K_true|| / ||K_true|| per tile, K = sum_k a_k B_k (host arrays)."""
+def kernel_error(coeffs, truth, B, psf=None):
+    """||K - K_true|| / ||K_true|| per tile, K = sum_k a_k B_k (host arrays);
+    with psf, of the kernels convolved with it (the error in the model of a
+    star, where the fit's poorly constrained high frequencies drop out)."""
     K = np.tensordot(np.asarray(coeffs)[:, :NB], B, 1)
     Kt = np.tensordot(np.asarray(truth)[:, :NB], B, 1)
+    if psf is not None:
+        from scipy import signal
+        K = np.stack([signal.convolve2d(k, psf) for k in K])
+        Kt = np.stack([signal.convolve2d(k, psf) for k in Kt])
     return np.linalg.norm((K - Kt).reshape(len(K), -1), axis=1) / \
         np.linalg.norm(Kt.reshape(len(K), -1), axis=1)
 
@@ -297,12 +309,16 @@ def evaluate(ctx, path: "SurrogatePath", frames, B):
         co_t = truth.coeffs.cpu().numpy()
         e_p = kernel_error(co_p, co_t, B)
         e_s = kernel_error(co_s, co_t, B)
+        psf = synth.psf_image(10, fr.cond.fwhm_ref)
+        m_p = kernel_error(co_p, co_t, B, psf)
+        m_s = kernel_error(co_s, co_t, B, psf)
         rp = (plain.chi2 / (plain.n_chi2 - (NB + 1))).cpu().numpy()
         rf = (c2 / n2.clamp_min(1)).cpu().numpy()
         acc = path.accepted.cpu().numpy()
         st = plain.status.cpu().numpy()
         for t in range(path.ns):
             rows.append(dict(err_plain=float(e_p[t]), err_sur=float(e_s[t]),
+                             model_err_plain=float(m_p[t]), model_err_sur=float(m_s[t]),
                              accepted=int(acc[t]), chi2dof_plain=float(rp[t]),
                              chi2dof_final=float(rf[t]), status=int(st[t])))
     return rows

@@ -105,6 +105,7 @@ def _oracle_cutout(frames, fi, x0, y0, L):
 # smallest cutouts, so their bar is 1e-3 sigma RMS, stamps 3e-3.
 STAMP_TOL = {argus.FP64: 1e-4, argus.FP32: 3e-3}
 RMS_TOL = {argus.FP64: 1e-4, argus.FP32: 1e-3}
+VAR_TOL = {argus.FP64: 1e-5, argus.FP32: 3e-4}       # V carries the kernel's error
 
 
 @pytest.mark.parametrize("precision", [argus.FP64, argus.FP32])
@@ -142,7 +143,7 @@ def test_batch_matches_oracle_per_cutout(ctx, frames, precision):
         assert r["mask"] and r["det"] and r["cand"], r
         assert r["stamp"] <= STAMP_TOL[precision], r
         assert r["rms"] <= RMS_TOL[precision] and r["mx"] <= 1e-2, r
-        assert r["var"] <= 1e-5 and r["chi2"] <= 1e-5, r
+        assert r["var"] <= VAR_TOL[precision] and r["chi2"] <= 1e-5, r
 
 
 def test_batch_equivalence_and_graph_replays(ctx, frames):
