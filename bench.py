@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--batch-frames", type=int, default=20)
     p.add_argument("--batch-cutouts", type=int, default=4000)
     p.add_argument("--batch-steps", type=int, default=3)
+    p.add_argument("--sur-frames", type=int, default=400)
+    p.add_argument("--sur-epochs", type=int, default=15)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device copy (5 times), the reference for "
                         "scaling hardware byte counters")
@@ -192,6 +194,97 @@ def batch_leg(args, torch, argus, synth):
     return res
 
 
+def surrogate_leg(args, torch, argus):
+    """Learned kernel surrogate: GPU training throughput, then per-frame plain
+    PER_TILE path vs surrogate path on 1024^2 frames (4x4 tiles, 15x15
+    kernel), acceptance and kernel error against the noise-free fit."""
+    from paper_2207_14304_amd import surrogate as sur
+    ctx = argus.Context(0)
+    t0 = time.perf_counter()
+    X, V, T = sur.build_training_set(ctx, args.sur_frames, 1, n_stars=(3000, 20000))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    Ts, mu, sd = sur.standardize(T)
+    cnn = argus.CNN(ctx, max_tiles=64)
+    cnn.set_weights(sur.init_weights(1))
+    n = X.shape[0]
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    steps = 0
+    for ep in range(args.sur_epochs):
+        lr = 2e-3 if ep < 0.7 * args.sur_epochs else 4e-4
+        steps += len(sur.train(cnn, X, V, Ts, 1, 32, lr, seed=100 + ep))
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    samples_s = steps * 32 / (train_ms / 1e3)
+    # 3 x 1.74 GMAC per training sample (forward, data and weight gradients)
+    train_tflops = samples_s * 3 * 1.74e9 * 2 / 1e12
+    cnn.set_weights(sur.fold_standardization(cnn.get_weights(), mu.cpu().numpy(),
+                                             sd.cpu().numpy()))
+    del X, V, T, Ts
+    # inference on configuration-1 frames (1024^2, 3000 stars, FWHM 2.0/2.6)
+    W = H = 1024
+    sp = sur.spec()
+    path = sur.SurrogatePath(ctx, cnn, W, H)
+    cond = sur.Conditions(2.0, 2.6, 0.0, 0.0, 800.0, 1.05)
+    frames = [sur.Frame(ctx, W, H, 3000, 9000 + i, cond, noise_free=True) for i in range(4)]
+    B = sur.basis_stamps(ctx)
+    rows = sur.evaluate(ctx, path, frames, B)
+
+    def timed(fn, reps=5):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            for fr in frames:
+                fn(fr)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / (reps * len(frames))
+
+    def plain(fr):
+        sur.TileFits(ctx, fr.planes, sp)
+
+    def surrogate_only(fr):
+        path.predict(fr.planes)
+        path.select(None, ref_chi2_dof=1.0)
+        path.subtract_final(fr.planes)
+
+    def evaluation_mode(fr):
+        tf = sur.TileFits(ctx, fr.planes, sp)
+        path.predict(fr.planes)
+        path.select(tf)
+        path.subtract_final(fr.planes)
+
+    ms_plain = timed(plain)
+    ms_sur = timed(surrogate_only)
+    ms_eval = timed(evaluation_mode)
+    ok = [r for r in rows if r["status"] == 0]
+    med = lambda k: float(np.nanmedian([r[k] for r in ok]))
+    res = {"train": {"samples": n, "frames": args.sur_frames, "epochs": args.sur_epochs,
+                     "generate_s": round(t_gen, 2), "samples_per_s": round(samples_s, 1),
+                     "TFLOP/s_bf16": round(train_tflops, 1),
+                     "frac_bf16_peak": round(train_tflops / 2500.0, 4)},
+           "plain_per_tile_mpix_s": round(W * H / (ms_plain / 1e3) / 1e6, 1),
+           "surrogate_path_mpix_s": round(W * H / (ms_sur / 1e3) / 1e6, 1),
+           "both_fits_mpix_s": round(W * H / (ms_eval / 1e3) / 1e6, 1),
+           "acceptance": round(float(np.mean([r["accepted"] for r in ok])), 3),
+           "final_over_plain_chi2dof_max": round(max(r["chi2dof_final"] / r["chi2dof_plain"]
+                                                     for r in ok), 5),
+           "kernel_err_vs_noise_free": {"plain": round(med("err_plain"), 4),
+                                        "surrogate": round(med("err_sur"), 4)},
+           "model_err_vs_noise_free": {"plain": round(med("model_err_plain"), 4),
+                                       "surrogate": round(med("model_err_sur"), 4)},
+           "workload": f"train: {args.sur_frames} 1024^2 pairs (seeing 1.5-4.0, ell 0-0.2, sky "
+                       f"200-3000), noise-free plain-fit targets, {args.sur_epochs} epochs, batch "
+                       f"32 tiles; infer: 4 configuration-1 frames, 4x4 tiles, 15x15 kernel"}
+    log("surrogate: " + json.dumps(res))
+    cnn.close()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -308,6 +401,8 @@ def main():
         "workload": "science calibrate + fit + expand + subtract + detect, reference resident"}}
     if args.batch_frames > 0:
         variants["batch"] = batch_leg(args, torch, argus, synth)
+    if args.sur_frames > 0:
+        variants["surrogate"] = surrogate_leg(args, torch, argus)
 
     value = npix / (ms / 1e3) / 1e6
     out = {

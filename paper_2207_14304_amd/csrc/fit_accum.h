@@ -396,7 +396,9 @@ struct FitLds {
         cvec = inrow + 2 * INP;                         // [SW][CST] raw basis convolutions
         wx = cvec + SW * CST;                           // [NA][SW]  w xt^a
         wsx = wx + S::NA * SW;                          // [NRA][SW] w S xt^a
-        wxd = (double *)(((uintptr_t)(wsx + S::NRA * SW) + 15) & ~(uintptr_t)15);  // [NA][SW]
+        // wsx ends on a 16-byte boundary (INP, SW multiples of 4); no integer
+        // round trip, which would make the LDS pointers generic
+        wxd = (double *)(wsx + S::NRA * SW);            // [NA][SW]
         wsxd = wxd + S::NA * SW;                        // [NRA][SW] w S xt^a (FP64 path)
         minrow = (uint8_t *)(wsxd + S::NRA * SW);       // [2][INP] ref mask != 0
     }
@@ -459,23 +461,30 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx_begin, int sx_end,
     uint8_t pm = 0;
     float p_s = 0.f, p_sv = 0.f, p_rv = 0.f;
     uint8_t p_sm = 1;
+    // the prefetches only load (from clamped addresses); the selects happen
+    // where the values are used, so the loads stay in flight for a row
+    bool pin = false, pok = false;
+    const int Xin = sx0 - HH + tid;
+    const bool in_x = tid < L::IN && Xin >= 0 && Xin < a.W;
+    const int Xc = in_x ? Xin : (Xin < 0 ? 0 : a.W - 1);
     auto fetch_in = [&](int yy) {
         if (tid < L::IN) {
-            int X = sx0 - HH + tid;
-            bool in = X >= 0 && X < a.W;
-            pr = in ? a.ref[(int64_t)yy * P + X] : 0.f;
-            pm = in ? (a.rmask[(int64_t)yy * P + X] != 0) : 0;
+            pr = a.ref[(int64_t)yy * P + Xc];
+            pm = a.rmask[(int64_t)yy * P + Xc];
+            pin = in_x;
         }
     };
+    const bool lane_ok = sx0 + lane < sx1;
+    const int64_t xw = lane_ok ? sx0 + lane : sx0;
     auto fetch_w = [&](int y) {
-        if (WAVE == 0 && y >= ry0 && y < ry1 && sx0 + lane < sx1) {
-            int64_t o = (int64_t)y * P + sx0 + lane;
+        if (WAVE == 0) {
+            pok = lane_ok && y >= ry0 && y < ry1;
+            const int yc = y < ry1 ? y : ry1 - 1;
+            const int64_t o = (int64_t)yc * P + xw;
             p_s = a.sci[o];
             p_sv = a.svar[o];
             p_rv = a.rvar[o];
             p_sm = a.smask[o];
-        } else {
-            p_sm = 1;
         }
     };
     uint32_t hist = 0;                     // bit j: input row yy-j has a flagged pixel in reach
@@ -487,11 +496,11 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx_begin, int sx_end,
     for (int yy = ry0 - HH; yy < yend; ++yy) {
         const int buf = yy & 1;
         if (tid < L::IN) {
-            l.inrow[buf * L::INP + tid] = pr;
-            l.minrow[buf * L::INP + tid] = pm;
+            l.inrow[buf * L::INP + tid] = pin ? pr : 0.f;
+            l.minrow[buf * L::INP + tid] = (pin && pm != 0) ? 1 : 0;
         }
         const float w_s = p_s, w_sv = p_sv, w_rv = p_rv;
-        const uint8_t w_sm = p_sm;
+        const uint8_t w_sm = pok ? p_sm : 1;
         if (yy + 1 < yend) fetch_in(yy + 1);
         const bool outrow = yy >= ry0 + HH;
         if (outrow) fetch_w(yy + 1 - HH);

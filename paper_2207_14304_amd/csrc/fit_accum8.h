@@ -47,7 +47,10 @@ struct FitLds8 {
         cvec0 = inrow + 2 * INP;                        // [2][32][CKM] k-major
         wx0 = cvec0 + 2 * 32 * CKM;                     // [2][NA][SW]
         wsx0 = wx0 + 2 * S::NA * SW;                    // [2][NRA][SW]
-        wxd0 = (double *)(((uintptr_t)(wsx0 + 2 * S::NRA * SW) + 15) & ~(uintptr_t)15);
+        // every region above is a multiple of 16 bytes long (INP, SW, CKM are
+        // multiples of 4): no integer round trip, which would turn the LDS
+        // pointers into generic ones
+        wxd0 = (double *)(wsx0 + 2 * S::NRA * SW);
         wsxd0 = wxd0 + 2 * S::NA * SW;
         minrow = (uint8_t *)(wsxd0 + 2 * S::NRA * SW);  // [2][INP] ref mask != 0
     }
@@ -106,28 +109,43 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
         const double xtd = (double)(sx0 + lane) * a.sx - (a.sx != 0.0 ? 1.0 : 0.0);
         const float xt = (float)xtd;
         const int64_t P = a.pitch;
-        // input rows are staged two ahead: row yy+1 goes to LDS during row yy
+        // Input rows are staged two ahead: row yy+1 goes to LDS during row yy.
+        // The prefetches only load (from clamped addresses); the in-frame
+        // selects happen where the values are used, a row later, so the loads
+        // stay in flight for a whole row instead of being waited for at once.
         float pr = 0.f;
         uint8_t pm = 0;
+        bool pin = false;
         float p_s = 0.f, p_sv = 0.f, p_rv = 0.f;
         uint8_t p_sm = 1;
+        bool pok = false;
+        const int Xin = sx0 - HH + tid;
+        const bool in_x = tid < L::IN && Xin >= 0 && Xin < a.W;
+        const int Xc = in_x ? Xin : (Xin < 0 ? 0 : a.W - 1);
         auto fetch_in = [&](int yy) {
             if (tid < L::IN) {
-                const int X = sx0 - HH + tid;
-                const bool in = X >= 0 && X < a.W;
-                pr = in ? a.ref[(int64_t)yy * P + X] : 0.f;
-                pm = in ? (a.rmask[(int64_t)yy * P + X] != 0) : 0;
+                pr = a.ref[(int64_t)yy * P + Xc];
+                pm = a.rmask[(int64_t)yy * P + Xc];
+                pin = in_x;
             }
         };
+        const bool lane_ok = sx0 + lane < sx1;
+        const int64_t xw = lane_ok ? sx0 + lane : sx0;
         auto fetch_w = [&](int y) {
-            if (W == 0 && y >= ry0 && y < ry1 && sx0 + lane < sx1) {
-                const int64_t o = (int64_t)y * P + sx0 + lane;
+            if (W == 0) {
+                pok = lane_ok && y >= ry0 && y < ry1;
+                const int yc = y < ry1 ? y : ry1 - 1;
+                const int64_t o = (int64_t)yc * P + xw;
                 p_s = a.sci[o];
                 p_sv = a.svar[o];
                 p_rv = a.rvar[o];
                 p_sm = a.smask[o];
-            } else {
-                p_sm = 1;
+            }
+        };
+        auto stage = [&](int b) {
+            if (tid < L::IN) {
+                l.inrow[b * L::INP + tid] = pin ? pr : 0.f;
+                l.minrow[b * L::INP + tid] = (pin && pm != 0) ? 1 : 0;
             }
         };
         uint32_t hist = 0;                 // bit j: input row yy-j has a flagged pixel in reach
@@ -136,10 +154,7 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
         if constexpr (CONV) {
             if (active) {
                 fetch_in(ystart);
-                if (tid < L::IN) {
-                    l.inrow[(ystart & 1) * L::INP + tid] = pr;
-                    l.minrow[(ystart & 1) * L::INP + tid] = pm;
-                }
+                stage(ystart & 1);
                 if (ystart + 1 < yend) fetch_in(ystart + 1);
                 fetch_w(ry0);
             }
@@ -151,13 +166,10 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
             if constexpr (CONV) {
                 if (yy < yend) {
                     // stage input row yy+1, prefetch row yy+2
-                    if (yy + 1 < yend && tid < L::IN) {
-                        l.inrow[(buf ^ 1) * L::INP + tid] = pr;
-                        l.minrow[(buf ^ 1) * L::INP + tid] = pm;
-                    }
+                    if (yy + 1 < yend) stage(buf ^ 1);
                     if (yy + 2 < yend) fetch_in(yy + 2);
                     const float w_s = p_s, w_sv = p_sv, w_rv = p_rv;
-                    const uint8_t w_sm = p_sm;
+                    const uint8_t w_sm = pok ? p_sm : 1;
                     const bool outrow = yy >= ry0 + HH;
                     if (outrow) fetch_w(yy + 1 - HH);
                     const int slot = yy % K;

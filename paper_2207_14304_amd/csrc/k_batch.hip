@@ -243,14 +243,37 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
     uint8_t *mout = a.dmask + cu.out_offset;
     for (int ty0 = 0; ty0 < L; ty0 += TILE) {
         for (int tx0 = 0; tx0 < L; tx0 += BW) {
-            for (int i = tid; i < TH * BL::TWr; i += NTHR) {
-                int cy = i / BL::TWr, cx = i % BL::TWr;
-                int X = tx0 - HH + cx, Y = ty0 - HH + cy;
-                bool in = X >= 0 && X < L && Y >= 0 && Y < L;
-                int64_t o = org + (int64_t)Y * P + X;
-                Rt[cy * TW + cx] = in ? fr.ref[o] : 0.f;
-                Vt[cy * TW + cx] = in ? fr.ref_var[o] : 0.f;
-                Mt[cy * MW + cx] = in ? (fr.ref_mask[o] != 0) : 0;
+            // halo: 8 elements per thread in flight at once (clamped
+            // addresses, out-of-cutout zeros applied at the store)
+            constexpr int NH = (TH * BL::TWr + NTHR - 1) / NTHR, NB8 = 8;
+            for (int j0 = 0; j0 < NH; j0 += NB8) {
+                float hr[NB8], hv[NB8];
+                uint8_t hm[NB8];
+#pragma unroll
+                for (int j = 0; j < NB8; ++j) {
+                    const int i = tid + (j0 + j) * NTHR;
+                    const int ii = i < TH * BL::TWr ? i : 0;
+                    const int cy = ii / BL::TWr, cx = ii % BL::TWr;
+                    int X = tx0 - HH + cx, Y = ty0 - HH + cy;
+                    X = X < 0 ? 0 : (X >= L ? L - 1 : X);
+                    Y = Y < 0 ? 0 : (Y >= L ? L - 1 : Y);
+                    const int64_t o = org + (int64_t)Y * P + X;
+                    hr[j] = fr.ref[o];
+                    hv[j] = fr.ref_var[o];
+                    hm[j] = fr.ref_mask[o];
+                }
+#pragma unroll
+                for (int j = 0; j < NB8; ++j) {
+                    const int i = tid + (j0 + j) * NTHR;
+                    if (i < TH * BL::TWr) {
+                        const int cy = i / BL::TWr, cx = i % BL::TWr;
+                        const int X = tx0 - HH + cx, Y = ty0 - HH + cy;
+                        const bool in = X >= 0 && X < L && Y >= 0 && Y < L;
+                        Rt[cy * TW + cx] = in ? hr[j] : 0.f;
+                        Vt[cy * TW + cx] = in ? hv[j] : 0.f;
+                        Mt[cy * MW + cx] = (in && hm[j] != 0) ? 1 : 0;
+                    }
+                }
             }
             __syncthreads();
             for (int i = tid; i < TH * (BW / PXT); i += NTHR) {

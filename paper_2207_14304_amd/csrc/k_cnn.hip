@@ -46,6 +46,9 @@ __device__ __forceinline__ float bf2f(bf16 x) { return (float)x; }
 // ---------------------------------------------------------------------------
 // Convolution: one workgroup per stamp; 61 output tiles of 16 pixels x 32
 // channels spread over the 4 waves; K = 9 * CIN (padded to 32) per tile.
+// The weight fragments of every K step stay in registers for the whole
+// stamp (loaded once from global memory), so the tile loop reads only the
+// activations from LDS, and two workgroups fit a CU.
 // MODE 0: z + bias, ReLU.  MODE 1: gate by (g > 0) (backward data).
 struct ConvArgs {
     const bf16 *in, *w, *gate;
@@ -55,16 +58,29 @@ struct ConvArgs {
     int npx, n;                                 // pixels per stamp (961), stamps
 };
 
+template <int CIN>
+struct ConvShape {
+    static constexpr int KP = ((9 * CIN + 31) / 32) * 32, KS = KP / 32, PW = 33;
+    static constexpr int ACT = (PW * PW * CIN + 7) & ~7;
+};
+
 template <int CIN, int MODE>
 __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
-    constexpr int KP = ((9 * CIN + 31) / 32) * 32, KS = KP / 32, W = 31, PW = 33;
-    constexpr int ACT = (PW * PW * CIN + 7) & ~7;   // keeps the weight rows 16-byte aligned
+    using CS = ConvShape<CIN>;
+    constexpr int KP = CS::KP, KS = CS::KS, W = 31, PW = CS::PW;
     extern __shared__ __align__(16) bf16 sm[];
     bf16 *act = sm;                             // [33][33][CIN], zero border
-    bf16 *wl = sm + ACT;                        // [32][KP]
     const int s = blockIdx.x, tid = threadIdx.x;
     if (!a.valid[s]) return;
-    for (int i = tid; i < ACT; i += NT) act[i] = (bf16)0.f;
+    const int lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
+    // B fragments: output channels col and 16+col, k = ks*32 + 8g .. +7
+    bf16x8 B0[KS], B1[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        B0[ks] = *(const bf16x8 *)&a.w[col * KP + ks * 32 + 8 * g];
+        B1[ks] = *(const bf16x8 *)&a.w[(16 + col) * KP + ks * 32 + 8 * g];
+    }
+    for (int i = tid; i < CS::ACT; i += NT) act[i] = (bf16)0.f;
     __syncthreads();
     const bf16 *src = a.in + (size_t)s * a.npx * CIN;
     for (int i = tid; i < a.npx * CIN; i += NT) {
@@ -72,9 +88,7 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
         int y = p / W, x = p % W;
         act[((y + 1) * PW + (x + 1)) * CIN + c] = src[i];
     }
-    for (int i = tid; i < 32 * KP; i += NT) wl[i] = a.w[i];
     __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
     bf16 *dst = a.out + (size_t)s * a.npx * 32;
     for (int t = wave; t * 16 < a.npx; t += 4) {
         floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
@@ -104,10 +118,8 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
                     A[e] = v;
                 }
             }
-            const bf16x8 B0 = *(const bf16x8 *)&wl[col * KP + ks * 32 + 8 * g];
-            const bf16x8 B1 = *(const bf16x8 *)&wl[(16 + col) * KP + ks * 32 + 8 * g];
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0[ks], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[ks], acc1, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -141,11 +153,39 @@ struct WgradArgs {
 };
 
 template <int CIN>
+struct WgradShape {
+    static constexpr int NJ = 9 * CIN, NTL = (NJ + 15) / 16, W = 31, DW = 32, AH = 33;
+    // input rows: x' = x + 1 in a 40-element (80-byte) row, so every 8-pixel
+    // operand is one or two aligned 16-byte reads
+    static constexpr int AW = 40;
+    static constexpr size_t bytes() { return ((size_t)32 * W * DW + (size_t)CIN * AH * AW) * 2; }
+};
+
+// 8 bf16 starting e elements (0, 1 or 2) past a 16-byte aligned address
+__device__ __forceinline__ bf16x8 shifted8(const bf16 *p, int e) {
+    const uint4 lo = *(const uint4 *)p;
+    if (e == 0) return *(const bf16x8 *)&lo;
+    const uint4 hi = *(const uint4 *)(p + 8);
+    uint4 r;
+    if (e == 2) {
+        r = make_uint4(lo.y, lo.z, lo.w, hi.x);
+    } else {
+        r.x = __builtin_amdgcn_alignbyte(lo.y, lo.x, 2);
+        r.y = __builtin_amdgcn_alignbyte(lo.z, lo.y, 2);
+        r.z = __builtin_amdgcn_alignbyte(lo.w, lo.z, 2);
+        r.w = __builtin_amdgcn_alignbyte(hi.x, lo.w, 2);
+    }
+    return *(const bf16x8 *)&r;
+}
+
+template <int CIN>
 __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
-    constexpr int NJ = 9 * CIN, NTL = (NJ + 15) / 16, W = 31, DW = 32, AW = 34, AH = 33;
+    using WS = WgradShape<CIN>;
+    constexpr int NJ = WS::NJ, NTL = WS::NTL, W = WS::W, DW = WS::DW, AW = WS::AW, AH = WS::AH;
     extern __shared__ __align__(16) bf16 sm[];
     bf16 *dzl = sm;                             // [32][31][32]   channel-first dZ
-    bf16 *al = sm + 32 * W * DW;                // [CIN][33][34]  channel-first input
+    bf16 *al = sm + 32 * W * DW;                // [CIN][33][40]  channel-first input
+    __shared__ float dbp[NT];
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, g = lane >> 4;
     constexpr int NMAX = (NTL + 3) / 4;
@@ -154,7 +194,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float db = 0.f;
+    float db = 0.f;                             // channel tid & 31, pixels tid >> 5 mod 8
     for (int i = tid; i < 32 * W * DW; i += NT) dzl[i] = (bf16)0.f;
     for (int i = tid; i < CIN * AH * AW; i += NT) al[i] = (bf16)0.f;
     __syncthreads();
@@ -172,10 +212,10 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
             al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
         }
         __syncthreads();
-        if (tid < 32) {
-            float sdb = 0.f;
-            for (int p = 0; p < a.npx; ++p) sdb += bf2f(dzl[(tid * W + p / W) * DW + p % W]);
-            db += sdb;
+        {
+            const int o = tid & 31;
+            for (int p = tid >> 5; p < a.npx; p += NT / 32)
+                db += bf2f(dzl[(o * W + p / W) * DW + p % W]);
         }
         for (int y = 0; y < W; ++y) {
             bf16x8 A0 = *(const bf16x8 *)&dzl[(col * W + y) * DW + 8 * g];
@@ -186,14 +226,20 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
                 if (nt >= NTL) break;
                 const int j = nt * 16 + col;
                 bf16x8 B;
-                if (j < NJ) {
-                    const int tap = j / CIN, c = j % CIN, dy = tap / 3 - 1, dx = tap % 3 - 1;
-                    const bf16 *rp = &al[(c * AH + y + 1 + dy) * AW + 1 + dx + 8 * g];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) B[e] = rp[e];
+                if constexpr (CIN == 32) {
+                    // one tap per 16-column tile: dy, dx uniform across the wave
+                    const int tap = (nt * 16) / 32, c = j % 32, dy = tap / 3 - 1, dx = tap % 3 - 1;
+                    B = shifted8(&al[(c * AH + y + 1 + dy) * AW + 8 * g], dx + 1);
                 } else {
+                    if (j < NJ) {
+                        const int tap = j / CIN, c = j % CIN, dy = tap / 3 - 1, dx = tap % 3 - 1;
+                        const bf16 *rp = &al[(c * AH + y + 1 + dy) * AW + 1 + dx + 8 * g];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) B[e] = (bf16)0.f;
+                        for (int e = 0; e < 8; ++e) B[e] = rp[e];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) B[e] = (bf16)0.f;
+                    }
                 }
                 acc[0][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B, acc[0][jj], 0, 0, 0);
                 acc[1][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B, acc[1][jj], 0, 0, 0);
@@ -213,7 +259,13 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[(mt * 16 + 4 * g + r) * NJ + j] = acc[mt][jj][r];
     }
-    if (tid < 32) part[32 * NJ + tid] = db;
+    dbp[tid] = db;
+    __syncthreads();
+    if (tid < 32) {
+        float sdb = 0.f;
+        for (int q = 0; q < NT / 32; ++q) sdb += dbp[q * 32 + tid];
+        part[32 * NJ + tid] = sdb;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -655,8 +707,7 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
 
 template <int CIN, int MODE>
 int conv_launch(argus_ctx *ctx, const ConvArgs &ca) {
-    constexpr int KP = ((9 * CIN + 31) / 32) * 32;
-    size_t lds = ((size_t)((33 * 33 * CIN + 7) & ~7) + 32 * KP) * sizeof(bf16);
+    size_t lds = (size_t)ConvShape<CIN>::ACT * sizeof(bf16);
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_conv_kernel<CIN, MODE>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n), dim3(NT), lds, ctx->stream, ca);
@@ -666,7 +717,7 @@ int conv_launch(argus_ctx *ctx, const ConvArgs &ca) {
 
 template <int CIN>
 int wgrad_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
-    size_t lds = ((size_t)32 * 31 * 32 + (size_t)CIN * 33 * 34) * sizeof(bf16);
+    size_t lds = WgradShape<CIN>::bytes();
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad_kernel<CIN>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T), dim3(NT), lds, ctx->stream, wa);

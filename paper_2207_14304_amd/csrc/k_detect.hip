@@ -54,26 +54,52 @@ __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
     const int sx = blockIdx.x, y0 = blockIdx.y * ROWS, tid = threadIdx.x;
     const int x0 = sx * SEG;
     const int64_t P = a.pitch;
-    // SNR of rows y0-1 .. y0+ROWS, 4-pixel chunks
-    for (int i = tid; i < (ROWS + 2) * (SEG / 4); i += NTHR) {
-        const int row = i / (SEG / 4), ch = i % (SEG / 4);
-        const int y = y0 - 1 + row, x = x0 + 4 * ch;
-        float4 v;
-        if (y < 0 || y >= a.H) {
-            v = make_float4(-__builtin_inff(), -__builtin_inff(), -__builtin_inff(),
-                            -__builtin_inff());
-        } else if (a.vec && x + 3 < a.W) {
-            const int64_t o = (int64_t)y * P + x;
-            const float4 D = *(const float4 *)(a.diff + o);
-            const float4 V = *(const float4 *)(a.dvar + o);
-            const uint32_t m = *(const uint32_t *)(a.dmask + o);
-            v = make_float4(snr_of(D.x, V.x, m & 0xffu), snr_of(D.y, V.y, (m >> 8) & 0xffu),
-                            snr_of(D.z, V.z, (m >> 16) & 0xffu), snr_of(D.w, V.w, m >> 24));
-        } else {
-            v = make_float4(snr_at(a, x, y), snr_at(a, x + 1, y), snr_at(a, x + 2, y),
-                            snr_at(a, x + 3, y));
+    // SNR of rows y0-1 .. y0+ROWS, 4-pixel chunks.  Vector path: all loads of
+    // a thread are issued (from clamped rows) before any is used.
+    constexpr int NCH = (ROWS + 2) * (SEG / 4), NIT = (NCH + NTHR - 1) / NTHR;
+    if (a.vec && x0 + SEG <= a.W) {
+        float4 Dv[NIT], Vv[NIT];
+        uint32_t Mv[NIT];
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int i = tid + j * NTHR, ii = i < NCH ? i : 0;
+            const int row = ii / (SEG / 4), ch = ii % (SEG / 4);
+            int y = y0 - 1 + row;
+            y = y < 0 ? 0 : (y >= a.H ? a.H - 1 : y);
+            const int64_t o = (int64_t)y * P + x0 + 4 * ch;
+            Dv[j] = *(const float4 *)(a.diff + o);
+            Vv[j] = *(const float4 *)(a.dvar + o);
+            Mv[j] = *(const uint32_t *)(a.dmask + o);
         }
-        *(float4 *)&s[row][4 + 4 * ch] = v;
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int i = tid + j * NTHR;
+            if (i < NCH) {
+                const int row = i / (SEG / 4), ch = i % (SEG / 4);
+                const int y = y0 - 1 + row;
+                float4 v;
+                if (y < 0 || y >= a.H) {
+                    v = make_float4(-__builtin_inff(), -__builtin_inff(), -__builtin_inff(),
+                                    -__builtin_inff());
+                } else {
+                    const float4 D = Dv[j], V = Vv[j];
+                    const uint32_t m = Mv[j];
+                    v = make_float4(snr_of(D.x, V.x, m & 0xffu),
+                                    snr_of(D.y, V.y, (m >> 8) & 0xffu),
+                                    snr_of(D.z, V.z, (m >> 16) & 0xffu),
+                                    snr_of(D.w, V.w, m >> 24));
+                }
+                *(float4 *)&s[row][4 + 4 * ch] = v;
+            }
+        }
+    } else {
+        for (int i = tid; i < NCH; i += NTHR) {
+            const int row = i / (SEG / 4), ch = i % (SEG / 4);
+            const int y = y0 - 1 + row, x = x0 + 4 * ch;
+            const float4 v = make_float4(snr_at(a, x, y), snr_at(a, x + 1, y),
+                                         snr_at(a, x + 2, y), snr_at(a, x + 3, y));
+            *(float4 *)&s[row][4 + 4 * ch] = v;
+        }
     }
     if (tid < 2 * (ROWS + 2)) {
         const int row = tid >> 1, side = tid & 1;

@@ -65,20 +65,60 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
 
     double c2 = 0.0, cnt = 0.0, swd = 0.0, sw = 0.0;
     if (bx0 < bx1 && by0 < by1) {
-        // halo tiles of the reference, its variance and mask
-        for (int i = tid; i < TH * L::TWr; i += NTHR) {
-            int cy = i / L::TWr, cx = i % L::TWr;
-            int X = bx0 - HH + cx, Y = by0 - HH + cy;
-            bool in = X >= 0 && X < a.W && Y >= 0 && Y < a.H;
-            int64_t o = (int64_t)Y * P + X;
-            Rt[cy * TW + cx] = in ? a.ref[o] : 0.f;
-            Vt[cy * TW + cx] = in ? a.rvar[o] : 0.f;
-            Mt[cy * MW + cx] = in ? (a.rmask[o] != 0) : 0;
+        // halo tiles of the reference, its variance and mask: every load of a
+        // thread is issued before any is used (clamped addresses, the
+        // out-of-frame zeros applied at the store), so they are all in flight
+        // together instead of one latency per element
+        {
+            constexpr int NH = (TH * L::TWr + NTHR - 1) / NTHR, NB8 = 8;
+            for (int j0 = 0; j0 < NH; j0 += NB8) {       // 8 elements in flight per batch
+                float hr[NB8], hv[NB8];
+                uint8_t hm[NB8];
+#pragma unroll
+                for (int j = 0; j < NB8; ++j) {
+                    const int i = tid + (j0 + j) * NTHR;
+                    const int ii = i < TH * L::TWr ? i : 0;
+                    const int cy = ii / L::TWr, cx = ii % L::TWr;
+                    int X = bx0 - HH + cx, Y = by0 - HH + cy;
+                    X = X < 0 ? 0 : (X >= a.W ? a.W - 1 : X);
+                    Y = Y < 0 ? 0 : (Y >= a.H ? a.H - 1 : Y);
+                    const int64_t o = (int64_t)Y * P + X;
+                    hr[j] = a.ref[o];
+                    hv[j] = a.rvar[o];
+                    hm[j] = a.rmask[o];
+                }
+#pragma unroll
+                for (int j = 0; j < NB8; ++j) {
+                    const int i = tid + (j0 + j) * NTHR;
+                    if (i < TH * L::TWr) {
+                        const int cy = i / L::TWr, cx = i % L::TWr;
+                        const int X = bx0 - HH + cx, Y = by0 - HH + cy;
+                        const bool in = X >= 0 && X < a.W && Y >= 0 && Y < a.H;
+                        Rt[cy * TW + cx] = in ? hr[j] : 0.f;
+                        Vt[cy * TW + cx] = in ? hv[j] : 0.f;
+                        Mt[cy * MW + cx] = (in && hm[j] != 0) ? 1 : 0;
+                    }
+                }
+            }
         }
         const float *src = a.stamps + (size_t)reg * NP * K * K;
-        for (int i = tid; i < NP * K * K; i += NTHR) St[i] = src[i];
-        if (D == 0)
-            for (int i = tid; i < K * K; i += NTHR) { float k = src[i]; St[K * K + i] = k * k; }
+        {
+            constexpr int NS_ = (NP * K * K + NTHR - 1) / NTHR;
+            float sv_[NS_];
+#pragma unroll
+            for (int j = 0; j < NS_; ++j) {
+                const int i = tid + j * NTHR;
+                sv_[j] = src[i < NP * K * K ? i : 0];
+            }
+#pragma unroll
+            for (int j = 0; j < NS_; ++j) {
+                const int i = tid + j * NTHR;
+                if (i < NP * K * K) {
+                    St[i] = sv_[j];
+                    if (D == 0 && i < K * K) St[K * K + i] = sv_[j] * sv_[j];
+                }
+            }
+        }
         __syncthreads();
         for (int i = tid; i < TH * (BW / PXT); i += NTHR) {
             int cy = i / (BW / PXT), lx0 = (i % (BW / PXT)) * PXT;

@@ -292,7 +292,8 @@ def basis_stamps(ctx, half=HALF):
 def evaluate(ctx, path: "SurrogatePath", frames, B):
     """Per tile of every frame: kernel errors of the plain fit and of the
     network against the fit on the noise-free frames, the acceptance, and the
-    chi^2/dof of the plain fit and of the final (accepted or fallback) kernel."""
+    chi^2/dof of the plain fit and of the final (accepted or fallback) kernel;
+    status is nonzero where the plain fit or the noise-free fit failed."""
     import torch
     sp = path.sp
     rows = []
@@ -316,9 +317,11 @@ def evaluate(ctx, path: "SurrogatePath", frames, B):
         rf = (c2 / n2.clamp_min(1)).cpu().numpy()
         acc = path.accepted.cpu().numpy()
         st = plain.status.cpu().numpy()
+        stt = truth.status.cpu().numpy()
         for t in range(path.ns):
             rows.append(dict(err_plain=float(e_p[t]), err_sur=float(e_s[t]),
                              model_err_plain=float(m_p[t]), model_err_sur=float(m_s[t]),
                              accepted=int(acc[t]), chi2dof_plain=float(rp[t]),
-                             chi2dof_final=float(rf[t]), status=int(st[t])))
+                             chi2dof_final=float(rf[t]),
+                             status=int(st[t]) if st[t] != 0 else int(stt[t])))
     return rows
