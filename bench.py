@@ -393,9 +393,32 @@ def main():
     ms_frame = f0.elapsed_time(f1) / args.steps
     log(f"per-frame difference: {ms_frame:.3f} ms")
 
+    # precision variants of the fit on the same frame: the fit accumulation
+    # time and the chi^2/dof of the subtraction each one gives, against FP32
+    prec = {}
+    chi = {}
+    for name, pv in (("fp32", argus.FP32), ("bf16x3", argus.BF16X3), ("fp64", argus.FP64)):
+        pipe.spec = argus.make_spec(sigmas=(0.7, 1.5, 3.0), degrees=(4, 3, 2), half_width=10,
+                                    spatial_degree=2, bg_degree=2, tiles_x=16, tiles_y=16,
+                                    precision=pv)
+        ctx.set_timing(True)
+        for _ in range(3):
+            pipe.fit()
+        t_fit = ctx.kernel_time_ms("fit_accum")
+        ctx.set_timing(False)
+        pipe.subtract()
+        c2 = float(pipe.chi2.sum().item()) / max(float(pipe.n_chi2.sum().item()) - 192, 1.0)
+        chi[name] = c2
+        prec[name] = {"fit_accum_ms": round(t_fit, 3),
+                      "status_ok": bool((pipe.status == 0).all().item())}
+    for name in prec:
+        prec[name]["chi2dof_over_fp32"] = round(chi[name] / chi["fp32"], 8)
+    pipe.spec = spec
+    log("precision variants: " + json.dumps(prec))
+
     del refs, sci, pipe
     torch.cuda.empty_cache()
-    variants = {"per_frame_difference": {
+    variants = {"precision": prec, "per_frame_difference": {
         "value": round(npix / (ms_frame / 1e3) / 1e6, 2), "unit": "Mpix/s",
         "ms": round(ms_frame, 4),
         "workload": "science calibrate + fit + expand + subtract + detect, reference resident"}}

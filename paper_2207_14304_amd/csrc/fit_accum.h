@@ -42,6 +42,7 @@ struct FitArgs {
     int stride;                // doubles per partial
     double sx, sy;             // 2/(W-1), 2/(H-1) (0 for a 1-pixel axis)
     int8_t plist[4][4];        // row-filter planes of each wave (-1: none)
+    int8_t plist8[8][2];       // the same for 8 convolution waves
 };
 
 __device__ __forceinline__ int qidx(int a, int b, int Dm) {   // a+b <= Dm, a outer
@@ -59,10 +60,11 @@ struct FitShape {
 
 // Per-wave MFMA work on one 64-pixel row: tasks t = WAVE, WAVE+4, ... with
 // a = t / 3 and block pair bp = t % 3 in {(0,0), (0,1), (1,1)}.
-template <int D, int WAVE, int PREC>
+template <int D, int WAVE, int PREC, int STR = 4>
 struct WaveGram {
+    // tasks t = WAVE, WAVE + STR, ... of the 3 (2D+1) (power, block pair) tasks
     static constexpr int NT = FitShape<D>::NT;
-    static constexpr int NTW = (NT - WAVE + 3) / 4;
+    static constexpr int NTW = (NT - WAVE + STR - 1) / STR;
     static constexpr int NB = 2 * D + 1;
     double F[NTW > 0 ? NTW : 1][NB][4];
 
@@ -79,7 +81,7 @@ struct WaveGram {
     __device__ void flush(const V (&acc)[NTW > 0 ? NTW : 1], const double *ypw) {
 #pragma unroll
         for (int j = 0; j < NTW; ++j) {
-            const int a = (WAVE + 4 * j) / 3;
+            const int a = (WAVE + STR * j) / 3;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 if (b <= 2 * D - a) {
@@ -107,7 +109,7 @@ struct WaveGram {
                     n0 = cvec[p * CST + col];
                     n1 = cvec[p * CST + 16 + col];
 #pragma unroll
-                    for (int j = 0; j < NTW; ++j) nw[j] = wx[((WAVE + 4 * j) / 3) * SW + p];
+                    for (int j = 0; j < NTW; ++j) nw[j] = wx[((WAVE + STR * j) / 3) * SW + p];
                 };
                 load(0);
 #pragma unroll
@@ -121,7 +123,7 @@ struct WaveGram {
                     const float c1 = r1 + g1 * cz;
 #pragma unroll
                     for (int j = 0; j < NTW; ++j) {
-                        const int t = WAVE + 4 * j;
+                        const int t = WAVE + STR * j;
                         const int bp = t % 3;
                         const float A = (bp == 2) ? c1 : c0;
                         const float B = wa[j] * ((bp == 0) ? c0 : c1);
@@ -141,7 +143,7 @@ struct WaveGram {
                     n0 = cvec[p * CST + col];
                     n1 = cvec[p * CST + 16 + col];
 #pragma unroll
-                    for (int j = 0; j < NTW; ++j) nw[j] = wxd[((WAVE + 4 * j) / 3) * SW + p];
+                    for (int j = 0; j < NTW; ++j) nw[j] = wxd[((WAVE + STR * j) / 3) * SW + p];
                 };
                 load(0);
 #pragma unroll
@@ -155,7 +157,7 @@ struct WaveGram {
                     if (s + 1 < SW / 4) load(s + 1);
 #pragma unroll
                     for (int j = 0; j < NTW; ++j) {
-                        const int t = WAVE + 4 * j;
+                        const int t = WAVE + STR * j;
                         const int bp = t % 3;
                         const double A = (bp == 2) ? c1 : c0;
                         const double B = wa[j] * ((bp == 0) ? c0 : c1);
@@ -186,7 +188,7 @@ struct WaveGram {
                     }
 #pragma unroll
                     for (int j = 0; j < NTW; ++j) {
-                        const int t = WAVE + 4 * j;
+                        const int t = WAVE + STR * j;
                         const int a = t / 3, bp = t % 3;
                         bf16x8 bh, bl;
 #pragma unroll
@@ -239,7 +241,7 @@ struct WaveGram {
                     if constexpr (PREC == ARGUS_FP32) {
 #pragma unroll
                         for (int j = 0; j < NTW; ++j) {
-                            const int a = (WAVE + 4 * j) / 3;
+                            const int a = (WAVE + STR * j) / 3;
                             const float4 w = *(const float4 *)(wx + a * SW + 16 * pk + 4 * u);
                             nw[j][0] = w.x; nw[j][1] = w.y; nw[j][2] = w.z; nw[j][3] = w.w;
                         }
@@ -262,7 +264,7 @@ struct WaveGram {
                     } else {
 #pragma unroll
                         for (int j = 0; j < NTW; ++j) {
-                            const int a = (WAVE + 4 * j) / 3;
+                            const int a = (WAVE + STR * j) / 3;
                             const double2 w0 = *(const double2 *)(wxd + a * SW + 16 * pk + 4 * u);
                             const double2 w1 = *(const double2 *)(wxd + a * SW + 16 * pk + 4 * u + 2);
                             w[j][0] = w0.x; w[j][1] = w0.y; w[j][2] = w1.x; w[j][3] = w1.y;
@@ -275,7 +277,7 @@ struct WaveGram {
                         const T c1 = (T)cb[e] + (T)g1 * (T)cz[e];
 #pragma unroll
                         for (int j = 0; j < NTW; ++j) {
-                            const int bp = (WAVE + 4 * j) % 3;
+                            const int bp = (WAVE + STR * j) % 3;
                             const T A = (bp == 2) ? c1 : c0;
                             const T B = w[j][e] * ((bp == 0) ? c0 : c1);
                             if constexpr (PREC == ARGUS_FP32)
@@ -318,7 +320,7 @@ struct WaveGram {
                     }
 #pragma unroll
                     for (int j = 0; j < NTW; ++j) {
-                        const int t = WAVE + 4 * j;
+                        const int t = WAVE + STR * j;
                         const int a = t / 3, bp = t % 3;
                         const float4 w0 = *(const float4 *)(wx + a * SW + p0);
                         const float4 w1 = *(const float4 *)(wx + a * SW + p0 + 4);
@@ -351,7 +353,7 @@ struct WaveGram {
             const int col = lane & 15, lg = lane >> 4;
 #pragma unroll
             for (int j = 0; j < NTW; ++j) {
-                const int t = WAVE + 4 * j;
+                const int t = WAVE + STR * j;
                 const int a = t / 3, bp = t % 3;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {

@@ -1,7 +1,6 @@
 // Wave-specialised form of the fused basis convolution + moment accumulation
-// for whole frames: 8 waves per workgroup, waves 0-3 convolve (row filters,
-// column filters, fit-set weights) and waves 4-7 accumulate the moments on
-// MFMA.  The convolution of output row y and the moments of row y-1 run at
+// for whole frames: NWC convolution waves (row filters, column filters,
+// fit-set weights) and NWM MFMA waves per workgroup.  The convolution of output row y and the moments of row y-1 run at
 // the same time on double-buffered operand tables, so every SIMD holds one
 // wave of each kind and its VALU and matrix pipes overlap; there is one
 // barrier per input row.
@@ -15,7 +14,6 @@
 
 namespace argus_fit {
 
-constexpr int NTHR8 = 512;
 
 template <int D, int HH>
 struct FitLds8 {
@@ -37,7 +35,7 @@ struct FitLds8 {
         using S = FitShape<D>;
         size_t w = (size_t)nplanes * K * SW + 2 * INP + 2 * 32 * CKM + 2 * (S::NA + S::NRA) * SW;
         size_t b = w * 4 + 16 + (size_t)2 * (S::NA + S::NRA) * SW * 8 + 2 * INP + 16;
-        size_t rhs = (size_t)8 * S::NR * 32 * 8 + 256;    // end-of-kernel reuse of rowbuf
+        size_t rhs = (size_t)16 * S::NR * 32 * 8 + 256;   // end-of-kernel reuse of rowbuf
         return (b > rhs ? b : rhs) + 64;
     }
     __device__ FitLds8(float *lds, int nplanes) {
@@ -56,23 +54,31 @@ struct FitLds8 {
     }
 };
 
-// Wave W of the workgroup: W < 4 convolves (planes plist[W]; wave 0 also
-// stages the fit-set weights), W >= 4 accumulates the tasks of WaveGram<W-4>.
-// Both roles walk the same rows and meet at the same barriers.
-template <int D, int HH, int W, int PREC>
+// Wave W of the workgroup: W < NWC convolves (its planes from plist, or
+// plist8 with 8 convolution waves; wave 0 also stages the fit-set weights),
+// W >= NWC accumulates the tasks W - NWC, W - NWC + NWM, ... on MFMA.  Both
+// roles walk the same rows and meet at the same barriers.
+template <int D, int HH, int W, int PREC, int NWC, int NWM>
 __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
                           int ry1, bool active, double *part) {
     using S = FitShape<D>;
     using L = FitLds8<D, HH>;
     constexpr int K = L::K;
-    constexpr bool CONV = W < 4;
-    constexpr int MW = CONV ? 0 : W - 4;
+    constexpr bool CONV = W < NWC;
+    constexpr int MW = CONV ? 0 : W - NWC;
+    constexpr int NPW = NWC == 4 ? 4 : 2;                // plane slots per convolution wave
+    constexpr int NTH = 64 * (NWC + NWM);
+    constexpr int PXW = SW / NWM, PXH = PXW / 2;         // rhs pixels per wave and half-wave
+    auto plane = [&](int j) -> int {
+        if constexpr (NWC == 4) return a.plist[W < 4 ? W : 0][j];
+        else return a.plist8[W < 8 ? W : 0][j];
+    };
     const int tid = threadIdx.x, lane = tid & 63;
     const int NPL = a.nplanes;
     L l(lds, NPL);
     double *rhsbuf = (double *)lds;
 
-    WaveGram<D, MW, PREC> gram;
+    WaveGram<D, MW, PREC, NWM> gram;
     double RF[S::NR];
     if constexpr (!CONV) {
         gram.zero();
@@ -82,13 +88,13 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
     int count = 0;
 
     // convolution waves: this wave's planes (wave-uniform)
-    int k0[4], nk[4];
+    int k0[NPW], nk[NPW];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NPW; ++j) {
         k0[j] = 0;
         nk[j] = 0;
         if constexpr (CONV) {
-            const int p = a.plist[W][j];
+            const int p = plane(j);
             if (p >= 0) {
                 for (int k = 0; k < a.nb; ++k)
                     if (a.tab->kpl[k] == p) {
@@ -179,8 +185,8 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
 #pragma unroll
                         for (int uu = 0; uu < K; ++uu) win[uu] = ir[2 * HH - uu];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int p = a.plist[W][j];
+                        for (int j = 0; j < NPW; ++j) {
+                            const int p = plane(j);
                             if (p >= 0) {
                                 const float *f = &a.tab->rowf[p][0];
                                 float acc = 0.f;
@@ -202,8 +208,8 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
                         const int s0 = (yy + 1) % K;
                         float *cv = l.cvec(buf);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int p = a.plist[W][j];
+                        for (int j = 0; j < NPW; ++j) {
+                            const int p = plane(j);
                             if (p >= 0) {
                                 float t[K];
 #pragma unroll
@@ -268,8 +274,8 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
 #pragma unroll
                         for (int e = 0; e < S::NRA; ++e) ra[e] = 0.0;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int px = MW * 16 + half * 8 + i;
+                        for (int i = 0; i < PXH; ++i) {
+                            const int px = MW * PXW + half * PXH + i;
                             const double c = (double)cv[k * L::CKM + px] + (double)gk * (double)cv[px];
 #pragma unroll
                             for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsxd(pb)[e * SW + px] * c;
@@ -284,8 +290,8 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
 #pragma unroll
                         for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int px = MW * 16 + half * 8 + i;
+                        for (int i = 0; i < PXH; ++i) {
+                            const int px = MW * PXW + half * PXH + i;
                             const float c = cv[k * L::CKM + px] + gk * cv[px];
 #pragma unroll
                             for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsx(pb)[e * SW + px] * c;
@@ -314,16 +320,28 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
         if (lane == 0) part[(size_t)S::NQ * 768 + S::NR * 32] = c;
     }
     __syncthreads();
-    for (int it = tid; it < S::NR * 32; it += NTHR8) {
+    for (int it = tid; it < S::NR * 32; it += NTH) {
         double s = 0.0;
-        for (int q = 0; q < 8; ++q) s += rhsbuf[q * S::NR * 32 + it];
+        for (int q = 0; q < 2 * NWM; ++q) s += rhsbuf[q * S::NR * 32 + it];
         part[(size_t)S::NQ * 768 + it] = s;
     }
 }
 
-template <int D, int HH, int PREC>
-__global__ __launch_bounds__(NTHR8) void fit_accum8_kernel(FitArgs a) {
+template <int D, int HH, int PREC, int NWC, int NWM, int W>
+__device__ __forceinline__ void fit_dispatch8(int w, const FitArgs &a, float *lds, int sx0, int sx1,
+                                              int ry0, int ry1, bool active, double *part) {
+    if constexpr (W < NWC + NWM) {
+        if (w == W)
+            fit_wave8<D, HH, W, PREC, NWC, NWM>(a, lds, sx0, sx1, ry0, ry1, active, part);
+        else
+            fit_dispatch8<D, HH, PREC, NWC, NWM, W + 1>(w, a, lds, sx0, sx1, ry0, ry1, active, part);
+    }
+}
+
+template <int D, int HH, int PREC, int NWC, int NWM>
+__global__ __launch_bounds__(64 * (NWC + NWM)) void fit_accum8_kernel(FitArgs a) {
     extern __shared__ __align__(16) float lds[];
+    constexpr int NTH = 64 * (NWC + NWM);
     const int tid = threadIdx.x;
     // workgroup -> region, strip, row chunk
     const int s = blockIdx.x % a.spt, rx = blockIdx.x / a.spt;
@@ -341,35 +359,30 @@ __global__ __launch_bounds__(NTHR8) void fit_accum8_kernel(FitArgs a) {
     double *part = a.partials + (size_t)pid * a.stride;
     // constant tail of c: 1 at index nb (background), zeros after, both buffers
     FitLds8<D, HH> L(lds, a.nplanes);
-    for (int i = tid; i < 2 * 32 * FitLds8<D, HH>::CKM; i += NTHR8) {
+    for (int i = tid; i < 2 * 32 * FitLds8<D, HH>::CKM; i += NTH) {
         const int k = (i / FitLds8<D, HH>::CKM) % 32;
         if (k >= a.nb) L.cvec0[i] = (k == a.nb) ? 1.f : 0.f;
     }
-    switch (tid >> 6) {
-        case 0: fit_wave8<D, HH, 0, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 1: fit_wave8<D, HH, 1, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 2: fit_wave8<D, HH, 2, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 3: fit_wave8<D, HH, 3, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 4: fit_wave8<D, HH, 4, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 5: fit_wave8<D, HH, 5, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        case 6: fit_wave8<D, HH, 6, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-        default: fit_wave8<D, HH, 7, PREC>(a, lds, sx0, sx1, ry0, ry1, active, part); break;
-    }
+    fit_dispatch8<D, HH, PREC, NWC, NWM, 0>(tid >> 6, a, lds, sx0, sx1, ry0, ry1, active, part);
 }
 
-// Launch fit_accum8_kernel<D, h, PREC> with its dynamic LDS size.
+// Launch fit_accum8_kernel<D, h, PREC, ...> with its dynamic LDS size: FP32
+// runs 8 convolution + 8 MFMA waves (two tasks each, so every wave fits in
+// 128 registers and each SIMD holds four waves); the FP64 and BF16x3 forms,
+// whose MFMA waves need more registers, run 4 + 4.
 template <int PREC>
 int fit_accum8_launch(argus_ctx *ctx, const FitArgs &fa, int D, dim3 grid) {
+    constexpr int NW = PREC == ARGUS_FP32 ? 8 : 4;
     hipError_t err = hipSuccess;
     bool ok = false;
 #define ARGUS_FH(DD, HH)                                                                   \
     if (D == DD && fa.h == HH) {                                                           \
         size_t lds = FitLds8<DD, HH>::bytes(fa.nplanes);                                   \
-        err = hipFuncSetAttribute((const void *)fit_accum8_kernel<DD, HH, PREC>,           \
+        err = hipFuncSetAttribute((const void *)fit_accum8_kernel<DD, HH, PREC, NW, NW>,   \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (err == hipSuccess)                                                             \
-            hipLaunchKernelGGL((fit_accum8_kernel<DD, HH, PREC>), grid, dim3(NTHR8), lds,  \
-                               ctx->stream, fa);                                           \
+            hipLaunchKernelGGL((fit_accum8_kernel<DD, HH, PREC, NW, NW>), grid,            \
+                               dim3(64 * 2 * NW), lds, ctx->stream, fa);                   \
         ok = true;                                                                         \
     }
 #define ARGUS_FD(DD)                                                                       \

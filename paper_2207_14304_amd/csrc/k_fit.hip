@@ -390,6 +390,22 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
             fa.plist[w][nin[w]++] = (int8_t)best;
             load[w] += cost[best];
         }
+        // the same for 8 convolution waves of at most 2 planes each
+        int load8[8] = {}, nin8[8] = {};
+        bool used8[ARGUS_MAX_PLANES] = {};
+        for (int w = 0; w < 8; ++w)
+            for (int j = 0; j < 2; ++j) fa.plist8[w][j] = -1;
+        for (int n = 0; n < fa.nplanes; ++n) {
+            int best = -1;
+            for (int q = 0; q < fa.nplanes; ++q)
+                if (!used8[q] && (best < 0 || cost[q] > cost[best])) best = q;
+            int w = -1;
+            for (int c = 0; c < 8; ++c)
+                if (nin8[c] < 2 && (w < 0 || load8[c] < load8[w])) w = c;
+            used8[best] = true;
+            fa.plist8[w][nin8[w]++] = (int8_t)best;
+            load8[w] += cost[best];
+        }
     }
     const bool global = spec->mode == ARGUS_FIT_GLOBAL;
     fa.RX = global ? 1 : spec->tiles_x;
