@@ -51,9 +51,11 @@ def parse():
 
 
 def copy_probe():
-    """A plain device-to-device copy of 1 GiB, five times: reads and writes
-    exactly 2^30 bytes each, so FETCH_SIZE / WRITE_SIZE counters of these
-    dispatches give the scale from counter units to bytes."""
+    """A plain elementwise copy kernel over 1 GiB (y = x * 1), five times: each
+    dispatch reads and writes exactly 2^30 bytes, so FETCH_SIZE / WRITE_SIZE
+    counters of these dispatches give the scale from counter units to bytes.
+    (An elementwise kernel rather than copy_, which may go to a DMA engine
+    that per-dispatch counters do not see.)"""
     import torch
     x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
@@ -61,7 +63,7 @@ def copy_probe():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(5):
-        y.copy_(x)
+        torch.mul(x, 1.0, out=y)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5

@@ -90,6 +90,8 @@ int argus_ctx_create(int device, argus_ctx **out) {
     if (hipSetDevice(device) != hipSuccess) return ARGUS_EHIP;
     argus_ctx *c = new argus_ctx();
     c->device = device;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        c->n_cu = 0;
     if (hipMalloc((void **)&c->tables, sizeof(BasisTables)) != hipSuccess) {
         delete c;
         return ARGUS_ENOMEM;

@@ -549,7 +549,7 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx_begin, int sx_end,
                         t[jj] = l.rowbuf[((size_t)p * K + sl) * SW + lane];
                     }
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) {
+                    for (int q = 0; q < 7; ++q) {
                         if (q < nk[j]) {
                             const float *f = &a.tab->colf[k0[j] + q][0];
                             float acc = 0.f;

@@ -1,29 +1,42 @@
 // Wave-specialised form of the fused basis convolution + moment accumulation
-// for whole frames: NWC convolution waves (row filters, column filters,
-// fit-set weights) and NWM MFMA waves per workgroup.  The convolution of output row y and the moments of row y-1 run at
-// the same time on double-buffered operand tables, so every SIMD holds one
-// wave of each kind and its VALU and matrix pipes overlap; there is one
-// barrier per input row.
+// for whole frames: 8 convolution waves (row filters, column filters,
+// fit-set weights) and NWM MFMA waves per workgroup.  The convolution of
+// output row y and the moments of row y-1 run at the same time on
+// double-buffered operand tables, so the VALU and matrix pipes of a SIMD
+// overlap; there is one barrier per input row.
+//
+// Convolution waves share one code path (their planes are data).  A lane
+// owns one output column: it keeps the last 2h+1 row-filtered values of each
+// of its planes in registers (a window that advances one row per step and is
+// re-based every U steps), so the column pass reads no LDS.  Both passes use
+// the symmetry of the filters, f(-u) = (-1)^i f(u): the taps at +-u are
+// added (even i) or subtracted (odd i) first, which halves the coefficients
+// a filter needs.
 //
 // The operand tables are k-major (c[k][p]) so that a lane's operands of
 // four consecutive MFMA steps are one 16-byte LDS read; the per-row sums
 // take the pixels in a different order than fit_wave, otherwise the
-// arithmetic (filters, products, FP64 flushes) is the same.
+// moments, products and FP64 flushes are those of fit_wave.
 #pragma once
+#include <type_traits>
 #include "fit_accum.h"
 
 namespace argus_fit {
 
+constexpr int U8 = 4;       // steps between re-basings of the column windows
+
+// Steps (and barriers) of a strip: n row steps padded to whole blocks of U8.
+__device__ __forceinline__ int fit8_steps(int n) { return (n + U8 - 1) / U8 * U8; }
 
 template <int D, int HH>
 struct FitLds8 {
     static constexpr int K = 2 * HH + 1;
     static constexpr int IN = SW + 2 * HH;               // input row length
     static constexpr int INP = (IN + 3) & ~3;
-    float *rowbuf, *inrow, *cvec0, *wx0, *wsx0;
-    double *wxd0, *wsxd0;
-    uint8_t *minrow;
     static constexpr int CKM = SW + 4;                   // k-major row stride of c
+    float *inrow, *cvec0, *wx0, *wsx0;
+    double *wxd0, *wsxd0;
+    uint64_t *mbits;                                     // [2][2] flagged input pixels
     // buffer b (0/1) of each double-buffered table (no pointer arrays: a
     // runtime index into one would place it in scratch)
     __device__ float *cvec(int b) const { return cvec0 + b * (32 * CKM); }
@@ -31,17 +44,16 @@ struct FitLds8 {
     __device__ float *wsx(int b) const { return wsx0 + b * (FitShape<D>::NRA * SW); }
     __device__ double *wxd(int b) const { return wxd0 + b * (FitShape<D>::NA * SW); }
     __device__ double *wsxd(int b) const { return wsxd0 + b * (FitShape<D>::NRA * SW); }
-    __host__ __device__ static size_t bytes(int nplanes) {
+    __host__ __device__ static size_t bytes(int nwm) {
         using S = FitShape<D>;
-        size_t w = (size_t)nplanes * K * SW + 2 * INP + 2 * 32 * CKM + 2 * (S::NA + S::NRA) * SW;
-        size_t b = w * 4 + 16 + (size_t)2 * (S::NA + S::NRA) * SW * 8 + 2 * INP + 16;
-        size_t rhs = (size_t)16 * S::NR * 32 * 8 + 256;   // end-of-kernel reuse of rowbuf
+        size_t w = 2 * INP + 2 * 32 * CKM + 2 * (S::NA + S::NRA) * SW;
+        size_t b = w * 4 + (size_t)2 * (S::NA + S::NRA) * SW * 8 + 4 * 8;
+        size_t rhs = (size_t)2 * nwm * S::NR * 32 * 8;   // end-of-kernel reuse
         return (b > rhs ? b : rhs) + 64;
     }
-    __device__ FitLds8(float *lds, int nplanes) {
+    __device__ FitLds8(float *lds) {
         using S = FitShape<D>;
-        rowbuf = lds;                                   // [NPL][K][SW]: thread-private columns
-        inrow = rowbuf + (size_t)nplanes * K * SW;      // [2][INP] double-buffered input row
+        inrow = lds;                                    // [2][INP] double-buffered input row
         cvec0 = inrow + 2 * INP;                        // [2][32][CKM] k-major
         wx0 = cvec0 + 2 * 32 * CKM;                     // [2][NA][SW]
         wsx0 = wx0 + 2 * S::NA * SW;                    // [2][NRA][SW]
@@ -50,65 +62,55 @@ struct FitLds8 {
         // pointers into generic ones
         wxd0 = (double *)(wsx0 + 2 * S::NRA * SW);
         wsxd0 = wxd0 + 2 * S::NA * SW;
-        minrow = (uint8_t *)(wsxd0 + 2 * S::NRA * SW);  // [2][INP] ref mask != 0
+        mbits = (uint64_t *)(wsxd0 + 2 * S::NRA * SW);
     }
 };
 
-// Wave W of the workgroup: W < NWC convolves (its planes from plist, or
-// plist8 with 8 convolution waves; wave 0 also stages the fit-set weights),
-// W >= NWC accumulates the tasks W - NWC, W - NWC + NWM, ... on MFMA.  Both
-// roles walk the same rows and meet at the same barriers.
-template <int D, int HH, int W, int PREC, int NWC, int NWM>
-__device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
-                          int ry1, bool active, double *part) {
+// Convolution wave cw (wave-uniform) of the NWC convolution waves, with up
+// to NP planes (from plist8 for 8 waves, plist for 4).  Wave 0 (W0) also
+// stages the fit-set weights (with 8 waves it takes one plane, so that its
+// registers fit the same budget); it returns the number of fit pixels it
+// counted, the others return 0.
+template <int D, int HH, int PREC, int NWC, int NP, bool W0>
+__device__ int fit_conv8(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
+                         int ry1, bool active, int cw) {
     using S = FitShape<D>;
     using L = FitLds8<D, HH>;
     constexpr int K = L::K;
-    constexpr bool CONV = W < NWC;
-    constexpr int MW = CONV ? 0 : W - NWC;
-    constexpr int NPW = NWC == 4 ? 4 : 2;                // plane slots per convolution wave
-    constexpr int NTH = 64 * (NWC + NWM);
-    constexpr int PXW = SW / NWM, PXH = PXW / 2;         // rhs pixels per wave and half-wave
-    auto plane = [&](int j) -> int {
-        if constexpr (NWC == 4) return a.plist[W < 4 ? W : 0][j];
-        else return a.plist8[W < 8 ? W : 0][j];
-    };
+    constexpr int NR_ = K - 1 + U8;                      // window registers per plane
     const int tid = threadIdx.x, lane = tid & 63;
-    const int NPL = a.nplanes;
-    L l(lds, NPL);
-    double *rhsbuf = (double *)lds;
-
-    WaveGram<D, MW, PREC, NWM> gram;
-    double RF[S::NR];
-    if constexpr (!CONV) {
-        gram.zero();
-#pragma unroll
-        for (int i = 0; i < S::NR; ++i) RF[i] = 0.0;
-    }
+    L l(lds);
     int count = 0;
 
-    // convolution waves: this wave's planes (wave-uniform)
-    int k0[NPW], nk[NPW];
+    // this wave's planes and their first basis function / basis count
+    int pl[NP], k0[NP], nk[NP];
+    float rc[NP][HH + 1];                                // row filter, taps 0..h
 #pragma unroll
-    for (int j = 0; j < NPW; ++j) {
+    for (int j = 0; j < NP; ++j) {
+        pl[j] = NWC == 8 ? a.plist8[cw][j] : a.plist[cw][j];
         k0[j] = 0;
         nk[j] = 0;
-        if constexpr (CONV) {
-            const int p = plane(j);
-            if (p >= 0) {
-                for (int k = 0; k < a.nb; ++k)
-                    if (a.tab->kpl[k] == p) {
-                        if (nk[j] == 0) k0[j] = k;
-                        ++nk[j];
-                    }
-            }
-            k0[j] = __builtin_amdgcn_readfirstlane(k0[j]);
-            nk[j] = __builtin_amdgcn_readfirstlane(nk[j]);
+        if (pl[j] >= 0) {
+            for (int k = 0; k < a.nb; ++k)
+                if (a.tab->kpl[k] == pl[j]) {
+                    if (nk[j] == 0) k0[j] = k;
+                    ++nk[j];
+                }
+        }
+        k0[j] = __builtin_amdgcn_readfirstlane(k0[j]);
+        nk[j] = __builtin_amdgcn_readfirstlane(nk[j]);
+        const int p = pl[j] >= 0 ? pl[j] : 0;
+#pragma unroll
+        for (int v = 0; v <= HH; ++v) {
+            rc[j][v] = uload(&a.tab->rowf[p][HH + v]);
         }
     }
-    const float g0 = (lane & 15) < a.nb ? a.tab->gam[lane & 15] : 0.f;
-    const float g1 = 16 + (lane & 15) < a.nb ? a.tab->gam[16 + (lane & 15)] : 0.f;
-    const float gk = (lane & 31) < a.nb ? a.tab->gam[lane & 31] : 0.f;  // rhs fix-up
+    // parity of each plane's row filter in x (odd filters vanish at u = 0)
+    bool odd[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+        odd[j] = __builtin_amdgcn_readfirstlane(pl[j] >= 0 ? a.tab->ipow[pl[j]] & 1 : 0) != 0;
+
     const int nstrips = active ? (sx_end - sx_begin + SW - 1) / SW : 1;
     for (int strip = 0; strip < nstrips; ++strip) {
         const int sx0 = sx_begin + strip * SW, sx1 = min(sx0 + SW, sx_end);
@@ -119,212 +121,274 @@ __device__ void fit_wave8(const FitArgs &a, float *lds, int sx_begin, int sx_end
         // The prefetches only load (from clamped addresses); the in-frame
         // selects happen where the values are used, a row later, so the loads
         // stay in flight for a whole row instead of being waited for at once.
+        // Waves 0 and 1 hold the IN input pixels.
         float pr = 0.f;
         uint8_t pm = 0;
-        bool pin = false;
         float p_s = 0.f, p_sv = 0.f, p_rv = 0.f;
         uint8_t p_sm = 1;
         bool pok = false;
-        const int Xin = sx0 - HH + tid;
-        const bool in_x = tid < L::IN && Xin >= 0 && Xin < a.W;
+        const bool stager = cw * 64 + lane < L::IN;
+        const int Xin = sx0 - HH + cw * 64 + lane;
+        const bool in_x = stager && Xin >= 0 && Xin < a.W;
         const int Xc = in_x ? Xin : (Xin < 0 ? 0 : a.W - 1);
         auto fetch_in = [&](int yy) {
-            if (tid < L::IN) {
+            if (cw < 2 && stager) {
                 pr = a.ref[(int64_t)yy * P + Xc];
                 pm = a.rmask[(int64_t)yy * P + Xc];
-                pin = in_x;
             }
         };
         const bool lane_ok = sx0 + lane < sx1;
         const int64_t xw = lane_ok ? sx0 + lane : sx0;
         auto fetch_w = [&](int y) {
-            if (W == 0) {
-                pok = lane_ok && y >= ry0 && y < ry1;
-                const int yc = y < ry1 ? y : ry1 - 1;
-                const int64_t o = (int64_t)yc * P + xw;
-                p_s = a.sci[o];
-                p_sv = a.svar[o];
-                p_rv = a.rvar[o];
-                p_sm = a.smask[o];
-            }
+            pok = lane_ok && y >= ry0 && y < ry1;
+            const int yc = y < ry1 ? y : ry1 - 1;
+            const int64_t o = (int64_t)yc * P + xw;
+            p_s = a.sci[o];
+            p_sv = a.svar[o];
+            p_rv = a.rvar[o];
+            p_sm = a.smask[o];
         };
         auto stage = [&](int b) {
-            if (tid < L::IN) {
-                l.inrow[b * L::INP + tid] = pin ? pr : 0.f;
-                l.minrow[b * L::INP + tid] = (pin && pm != 0) ? 1 : 0;
+            if (cw < 2) {
+                const bool f = stager && in_x && pm != 0;
+                const uint64_t bits = __ballot(f);
+                if (stager) l.inrow[b * L::INP + cw * 64 + lane] = in_x ? pr : 0.f;
+                if (lane == 0) l.mbits[2 * b + cw] = bits;
             }
         };
         uint32_t hist = 0;                 // bit j: input row yy-j has a flagged pixel in reach
         const int ystart = ry0 - HH;
         const int yend = active ? ry1 + HH : ystart;
-        if constexpr (CONV) {
-            if (active) {
-                fetch_in(ystart);
-                stage(ystart & 1);
-                if (ystart + 1 < yend) fetch_in(ystart + 1);
-                fetch_w(ry0);
-            }
+        if (active) {
+            fetch_in(ystart);
+            stage(ystart & 1);
+            if (ystart + 1 < yend) fetch_in(ystart + 1);
+            if (W0) fetch_w(ry0);
         }
         __syncthreads();
-        // one extra step drains the last output row into the moments
-        for (int yy = ystart; yy <= yend; ++yy) {
+        float rw[NP][NR_];                 // column windows: rw[j][u .. u+K-1] at sub-step u
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+#pragma unroll
+            for (int i = 0; i < NR_; ++i) rw[j][i] = 0.f;
+
+        // One step: input row yy (sub-step u of a block of U8).  Steps at and
+        // after yend only keep the barrier count; their row pass runs on stale
+        // LDS data (in bounds) into window slots that no output uses, which
+        // keeps the window registers free of conditional updates.
+        auto step = [&](auto uc, int yy) {
+            constexpr int u = decltype(uc)::value;
             const int buf = yy & 1;
-            if constexpr (CONV) {
-                if (yy < yend) {
-                    // stage input row yy+1, prefetch row yy+2
-                    if (yy + 1 < yend) stage(buf ^ 1);
-                    if (yy + 2 < yend) fetch_in(yy + 2);
-                    const float w_s = p_s, w_sv = p_sv, w_rv = p_rv;
-                    const uint8_t w_sm = pok ? p_sm : 1;
-                    const bool outrow = yy >= ry0 + HH;
-                    if (outrow) fetch_w(yy + 1 - HH);
-                    const int slot = yy % K;
-                    {
-                        float win[K];
-                        const float *ir = l.inrow + buf * L::INP + lane;
+            const bool live = yy < yend;
+            if (live) {
+                if (yy + 1 < yend) stage(buf ^ 1);
+                if (yy + 2 < yend) fetch_in(yy + 2);
+            }
+            const float w_s = p_s, w_sv = p_sv, w_rv = p_rv;
+            const uint8_t w_sm = pok ? p_sm : 1;
+            const bool outrow = live && yy >= ry0 + HH;
+            if (W0 && outrow) fetch_w(yy + 1 - HH);
+            {
+                // row pass: taps +-v of the input row paired
+                {
+                    const float *ir = l.inrow + buf * L::INP + lane + HH;
+                    float sp[HH + 1], sm[HH + 1];
+                    const float c = ir[0];
 #pragma unroll
-                        for (int uu = 0; uu < K; ++uu) win[uu] = ir[2 * HH - uu];
-#pragma unroll
-                        for (int j = 0; j < NPW; ++j) {
-                            const int p = plane(j);
-                            if (p >= 0) {
-                                const float *f = &a.tab->rowf[p][0];
-                                float acc = 0.f;
-#pragma unroll
-                                for (int uu = 0; uu < K; ++uu) acc += uload(f + uu) * win[uu];
-                                l.rowbuf[((size_t)p * K + slot) * SW + lane] = acc;
-                            }
-                        }
-                        if (W == 0) {
-                            const uint8_t *mr = l.minrow + buf * L::INP + lane;
-                            uint8_t m = 0;
-#pragma unroll
-                            for (int uu = 0; uu < K; ++uu) m |= mr[uu];
-                            hist = (hist << 1) | (m ? 1u : 0u);
-                        }
+                    for (int v = 1; v <= HH; ++v) {
+                        const float lo = ir[-v], hi = ir[v];
+                        sp[v] = lo + hi;
+                        sm[v] = lo - hi;
                     }
-                    if (outrow) {
-                        // column filters: rows y-h..y+h sit in slots (yy+1 .. yy+K) mod K
-                        const int s0 = (yy + 1) % K;
-                        float *cv = l.cvec(buf);
 #pragma unroll
-                        for (int j = 0; j < NPW; ++j) {
-                            const int p = plane(j);
-                            if (p >= 0) {
-                                float t[K];
+                    for (int j = 0; j < NP; ++j) {
+                        float acc;
+                        if (odd[j]) {
+                            acc = rc[j][1] * sm[1];
 #pragma unroll
-                                for (int jj = 0; jj < K; ++jj) {
-                                    int sl = s0 + jj;
-                                    sl -= sl >= K ? K : 0;
-                                    t[jj] = l.rowbuf[((size_t)p * K + sl) * SW + lane];
+                            for (int v = 2; v <= HH; ++v) acc += rc[j][v] * sm[v];
+                        } else {
+                            acc = rc[j][0] * c;
+#pragma unroll
+                            for (int v = 1; v <= HH; ++v) acc += rc[j][v] * sp[v];
+                        }
+                        rw[j][K - 1 + u] = acc;
+                    }
+                }
+                if (W0 && live) {
+                    // flagged reference pixel within +-h of this column
+                    const uint64_t b0 = l.mbits[2 * buf], b1 = l.mbits[2 * buf + 1];
+                    const uint64_t lo = (b0 >> lane) | ((b1 << (63 - lane)) << 1);
+                    const bool m = (lo & ((1ull << K) - 1ull)) != 0;
+                    hist = (hist << 1) | (m ? 1u : 0u);
+                }
+                if (outrow) {
+                    // column pass: rows y-h..y+h are rw[j][u .. u+2h]
+                    float *cv = l.cvec(buf);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        if (nk[j] > 0) {
+                            // even column powers on the paired sums, then odd
+                            // ones on the paired differences
+                            float e[HH + 1];
+                            e[0] = rw[j][u + HH];
+#pragma unroll
+                            for (int v = 1; v <= HH; ++v) e[v] = rw[j][u + HH - v] + rw[j][u + HH + v];
+#pragma unroll
+                            for (int q = 0; q < 7; q += 2) {
+                                if (q < nk[j]) {
+                                    const float *f = &a.tab->colf[k0[j] + q][HH];
+                                    float acc = uload(f) * e[0];
+#pragma unroll
+                                    for (int v = 1; v <= HH; ++v) acc += uload(f + v) * e[v];
+                                    cv[(k0[j] + q) * L::CKM + lane] = acc;
                                 }
+                            }
+                            if (nk[j] > 1) {
 #pragma unroll
-                                for (int q = 0; q < 5; ++q) {
+                                for (int v = 1; v <= HH; ++v) e[v] = rw[j][u + HH - v] - rw[j][u + HH + v];
+#pragma unroll
+                                for (int q = 1; q < 7; q += 2) {
                                     if (q < nk[j]) {
-                                        const float *f = &a.tab->colf[k0[j] + q][0];
-                                        float acc = 0.f;
+                                        const float *f = &a.tab->colf[k0[j] + q][HH];
+                                        float acc = uload(f + 1) * e[1];
 #pragma unroll
-                                        for (int jj = 0; jj < K; ++jj)
-                                            acc += uload(f + 2 * HH - jj) * t[jj];
+                                        for (int v = 2; v <= HH; ++v) acc += uload(f + v) * e[v];
                                         cv[(k0[j] + q) * L::CKM + lane] = acc;
                                     }
                                 }
                             }
                         }
-                        if (W == 0) {
-                            const bool foot = (hist & ((1u << K) - 1u)) != 0;
-                            const float tot = w_sv + w_rv;
-                            float w = 0.f;
-                            if (w_sm == 0 && !foot && tot > 0.f) {
-                                w = 1.0f / tot;
-                                ++count;
-                            }
-                            float xp = 1.f;
-                            double xpd = 1.0;
+                    }
+                    if (W0) {
+                        const bool foot = (hist & ((1u << K) - 1u)) != 0;
+                        const float tot = w_sv + w_rv;
+                        float w = 0.f;
+                        if (w_sm == 0 && !foot && tot > 0.f) {
+                            w = 1.0f / tot;
+                            ++count;
+                        }
+                        float xp = 1.f;
+                        double xpd = 1.0;
 #pragma unroll
-                            for (int e = 0; e < S::NA; ++e) {
-                                l.wx(buf)[e * SW + lane] = w * xp;
-                                if (PREC == ARGUS_FP64) l.wxd(buf)[e * SW + lane] = (double)w * xpd;
-                                if (e < S::NRA) l.wsx(buf)[e * SW + lane] = w * w_s * xp;
-                                if (PREC == ARGUS_FP64 && e < S::NRA)
-                                    l.wsxd(buf)[e * SW + lane] = (double)w * (double)w_s * xpd;
-                                xp *= xt;
-                                xpd *= xtd;
-                            }
+                        for (int e = 0; e < S::NA; ++e) {
+                            l.wx(buf)[e * SW + lane] = w * xp;
+                            if (PREC == ARGUS_FP64) l.wxd(buf)[e * SW + lane] = (double)w * xpd;
+                            if (e < S::NRA) l.wsx(buf)[e * SW + lane] = w * w_s * xp;
+                            if (PREC == ARGUS_FP64 && e < S::NRA)
+                                l.wsxd(buf)[e * SW + lane] = (double)w * (double)w_s * xpd;
+                            xp *= xt;
+                            xpd *= xtd;
                         }
                     }
                 }
-            } else {
-                // moments of output row y = yy - 1 - h, written during the previous step
-                const int y = yy - 1 - HH;
-                if (yy - 1 >= ry0 + HH && yy - 1 < yend) {
-                    const int pb = buf ^ 1;
-                    double ypw[2 * D + 1];
-                    {
-                        const double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
-                        double yp = 1.0;
+            }
+            __syncthreads();
+        };
+        // one extra step drains the last output row into the moments; the
+        // step count is padded to whole blocks (the MFMA waves pad alike)
+        const int ylast = ystart + fit8_steps(yend - ystart + 1) - 1;
+        for (int yy = ystart; yy <= ylast; yy += U8) {
+            step(std::integral_constant<int, 0>{}, yy);
+            step(std::integral_constant<int, 1>{}, yy + 1);
+            step(std::integral_constant<int, 2>{}, yy + 2);
+            step(std::integral_constant<int, 3>{}, yy + 3);
+            // re-base the windows: the newest K-1 rows move to the front
 #pragma unroll
-                        for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
+            for (int j = 0; j < NP; ++j)
+#pragma unroll
+                for (int i = 0; i < K - 1; ++i) rw[j][i] = rw[j][i + U8];
+        }
+    }
+    return count;
+}
+
+// MFMA wave W (NWC <= W < NWC + NWM) of the workgroup: the moments of the
+// previous output row from the tables the convolution waves wrote, and the
+// right-hand-side pieces of its pixels.
+template <int D, int HH, int W, int PREC, int NWC, int NWM>
+__device__ void fit_mfma8(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
+                          int ry1, bool active, double *part) {
+    using S = FitShape<D>;
+    using L = FitLds8<D, HH>;
+    constexpr int MW = W - NWC;
+    constexpr int PXW = SW / NWM, PXH = PXW / 2;         // rhs pixels per wave and half-wave
+    const int tid = threadIdx.x, lane = tid & 63;
+    L l(lds);
+    double *rhsbuf = (double *)lds;
+
+    WaveGram<D, MW, PREC, NWM> gram;
+    double RF[S::NR];
+    gram.zero();
+#pragma unroll
+    for (int i = 0; i < S::NR; ++i) RF[i] = 0.0;
+    const float g0 = (lane & 15) < a.nb ? a.tab->gam[lane & 15] : 0.f;
+    const float g1 = 16 + (lane & 15) < a.nb ? a.tab->gam[16 + (lane & 15)] : 0.f;
+    const float gk = (lane & 31) < a.nb ? a.tab->gam[lane & 31] : 0.f;  // rhs fix-up
+    const int nstrips = active ? (sx_end - sx_begin + SW - 1) / SW : 1;
+    for (int strip = 0; strip < nstrips; ++strip) {
+        const int ystart = ry0 - HH;
+        const int yend = active ? ry1 + HH : ystart;
+        const int ylast = ystart + fit8_steps(yend - ystart + 1) - 1;
+        __syncthreads();
+        for (int yy = ystart; yy <= ylast; ++yy) {
+            const int buf = yy & 1;
+            // moments of output row y = yy - 1 - h, written during the previous step
+            const int y = yy - 1 - HH;
+            if (yy - 1 >= ry0 + HH && yy - 1 < yend) {
+                const int pb = buf ^ 1;
+                double ypw[2 * D + 1];
+                {
+                    const double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
+                    double yp = 1.0;
+#pragma unroll
+                    for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
+                }
+                gram.row_km(l.cvec(pb), l.wx(pb), l.wxd(pb), ypw, lane, g0, g1);
+                const float *cv = l.cvec(pb);
+                const int k = lane & 31, half = lane >> 5;
+                if constexpr (PREC == ARGUS_FP64) {
+                    double ra[S::NRA];
+#pragma unroll
+                    for (int e = 0; e < S::NRA; ++e) ra[e] = 0.0;
+#pragma unroll
+                    for (int i = 0; i < PXH; ++i) {
+                        const int px = MW * PXW + half * PXH + i;
+                        const double c = (double)cv[k * L::CKM + px] + (double)gk * (double)cv[px];
+#pragma unroll
+                        for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsxd(pb)[e * SW + px] * c;
                     }
-                    gram.row_km(l.cvec(pb), l.wx(pb), l.wxd(pb), ypw, lane, g0, g1);
-                    const float *cv = l.cvec(pb);
-                    const int k = lane & 31, half = lane >> 5;
-                    if constexpr (PREC == ARGUS_FP64) {
-                        double ra[S::NRA];
 #pragma unroll
-                        for (int e = 0; e < S::NRA; ++e) ra[e] = 0.0;
+                    for (int e = 0; e < S::NRA; ++e)
 #pragma unroll
-                        for (int i = 0; i < PXH; ++i) {
-                            const int px = MW * PXW + half * PXH + i;
-                            const double c = (double)cv[k * L::CKM + px] + (double)gk * (double)cv[px];
+                        for (int b = 0; b <= D; ++b)
+                            if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * ra[e];
+                } else {
+                    float ra[S::NRA];
 #pragma unroll
-                            for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsxd(pb)[e * SW + px] * c;
-                        }
+                    for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
 #pragma unroll
-                        for (int e = 0; e < S::NRA; ++e)
+                    for (int i = 0; i < PXH; ++i) {
+                        const int px = MW * PXW + half * PXH + i;
+                        const float c = cv[k * L::CKM + px] + gk * cv[px];
 #pragma unroll
-                            for (int b = 0; b <= D; ++b)
-                                if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * ra[e];
-                    } else {
-                        float ra[S::NRA];
-#pragma unroll
-                        for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
-#pragma unroll
-                        for (int i = 0; i < PXH; ++i) {
-                            const int px = MW * PXW + half * PXH + i;
-                            const float c = cv[k * L::CKM + px] + gk * cv[px];
-#pragma unroll
-                            for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsx(pb)[e * SW + px] * c;
-                        }
-#pragma unroll
-                        for (int e = 0; e < S::NRA; ++e)
-#pragma unroll
-                            for (int b = 0; b <= D; ++b)
-                                if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
+                        for (int e = 0; e < S::NRA; ++e) ra[e] += l.wsx(pb)[e * SW + px] * c;
                     }
+#pragma unroll
+                    for (int e = 0; e < S::NRA; ++e)
+#pragma unroll
+                        for (int b = 0; b <= D; ++b)
+                            if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
                 }
             }
             __syncthreads();
         }
     }
-    // partials: moments (MFMA waves), rhs pieces through LDS, fit-set count
-    if constexpr (!CONV) {
-        gram.store(part, lane);
-        const int k = lane & 31, half = lane >> 5;
+    // partials: moments, rhs pieces through LDS (summed by the whole workgroup)
+    gram.store(part, lane);
+    const int k = lane & 31, half = lane >> 5;
 #pragma unroll
-        for (int i = 0; i < S::NR; ++i) rhsbuf[((MW * 2 + half) * S::NR + i) * 32 + k] = RF[i];
-    }
-    if constexpr (W == 0) {
-        double c = (double)count;
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-        if (lane == 0) part[(size_t)S::NQ * 768 + S::NR * 32] = c;
-    }
-    __syncthreads();
-    for (int it = tid; it < S::NR * 32; it += NTH) {
-        double s = 0.0;
-        for (int q = 0; q < 2 * NWM; ++q) s += rhsbuf[q * S::NR * 32 + it];
-        part[(size_t)S::NQ * 768 + it] = s;
-    }
+    for (int i = 0; i < S::NR; ++i) rhsbuf[((MW * 2 + half) * S::NR + i) * 32 + k] = RF[i];
 }
 
 template <int D, int HH, int PREC, int NWC, int NWM, int W>
@@ -332,7 +396,7 @@ __device__ __forceinline__ void fit_dispatch8(int w, const FitArgs &a, float *ld
                                               int ry0, int ry1, bool active, double *part) {
     if constexpr (W < NWC + NWM) {
         if (w == W)
-            fit_wave8<D, HH, W, PREC, NWC, NWM>(a, lds, sx0, sx1, ry0, ry1, active, part);
+            fit_mfma8<D, HH, W, PREC, NWC, NWM>(a, lds, sx0, sx1, ry0, ry1, active, part);
         else
             fit_dispatch8<D, HH, PREC, NWC, NWM, W + 1>(w, a, lds, sx0, sx1, ry0, ry1, active, part);
     }
@@ -341,8 +405,12 @@ __device__ __forceinline__ void fit_dispatch8(int w, const FitArgs &a, float *ld
 template <int D, int HH, int PREC, int NWC, int NWM>
 __global__ __launch_bounds__(64 * (NWC + NWM)) void fit_accum8_kernel(FitArgs a) {
     extern __shared__ __align__(16) float lds[];
+    using S = FitShape<D>;
     constexpr int NTH = 64 * (NWC + NWM);
+    // planes per convolution wave: 8 waves take 1 (wave 0) or 2, 4 waves up to 4
+    constexpr int NP0 = NWC == 8 ? 1 : 4, NP = NWC == 8 ? 2 : 4;
     const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     // workgroup -> region, strip, row chunk
     const int s = blockIdx.x % a.spt, rx = blockIdx.x / a.spt;
     const int rc = blockIdx.y % a.rchunks, ry = blockIdx.y / a.rchunks;
@@ -358,31 +426,51 @@ __global__ __launch_bounds__(64 * (NWC + NWM)) void fit_accum8_kernel(FitArgs a)
     const int pid = ((ry * a.RX + rx) * a.rchunks + rc) * a.spt + s;
     double *part = a.partials + (size_t)pid * a.stride;
     // constant tail of c: 1 at index nb (background), zeros after, both buffers
-    FitLds8<D, HH> L(lds, a.nplanes);
+    FitLds8<D, HH> L(lds);
     for (int i = tid; i < 2 * 32 * FitLds8<D, HH>::CKM; i += NTH) {
         const int k = (i / FitLds8<D, HH>::CKM) % 32;
         if (k >= a.nb) L.cvec0[i] = (k == a.nb) ? 1.f : 0.f;
     }
-    fit_dispatch8<D, HH, PREC, NWC, NWM, 0>(tid >> 6, a, lds, sx0, sx1, ry0, ry1, active, part);
+    int count = 0;
+    if (w == 0)
+        count = fit_conv8<D, HH, PREC, NWC, NP0, true>(a, lds, sx0, sx1, ry0, ry1, active, 0);
+    else if (w < NWC)
+        fit_conv8<D, HH, PREC, NWC, NP, false>(a, lds, sx0, sx1, ry0, ry1, active, w);
+    else
+        fit_dispatch8<D, HH, PREC, NWC, NWM, NWC>(w, a, lds, sx0, sx1, ry0, ry1, active, part);
+    if (w == 0) {
+        const int lane = tid & 63;
+        double c = (double)count;
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if (lane == 0) part[(size_t)S::NQ * 768 + S::NR * 32] = c;
+    }
+    __syncthreads();
+    const double *rhsbuf = (const double *)lds;
+    for (int it = tid; it < S::NR * 32; it += NTH) {
+        double acc = 0.0;
+        for (int q = 0; q < 2 * NWM; ++q) acc += rhsbuf[q * S::NR * 32 + it];
+        part[(size_t)S::NQ * 768 + it] = acc;
+    }
 }
 
-// Launch fit_accum8_kernel<D, h, PREC, ...> with its dynamic LDS size: FP32
-// runs 8 convolution + 8 MFMA waves (two tasks each, so every wave fits in
-// 128 registers and each SIMD holds four waves); the FP64 and BF16x3 forms,
-// whose MFMA waves need more registers, run 4 + 4.
+// Launch fit_accum8_kernel<D, h, PREC, NWC, NWM> with its dynamic LDS size:
+// FP32 runs 8 convolution + 8 MFMA waves (two tasks each, so every wave fits
+// in 128 registers and each SIMD holds four waves); the FP64 and BF16x3
+// forms, whose MFMA waves hold four tasks' FP64 sums, run 4 + 4.
 template <int PREC>
 int fit_accum8_launch(argus_ctx *ctx, const FitArgs &fa, int D, dim3 grid) {
-    constexpr int NW = PREC == ARGUS_FP32 ? 8 : 4;
+    constexpr int NWM = PREC == ARGUS_FP32 ? 8 : 4;
+    constexpr int NWC = PREC == ARGUS_FP32 ? 8 : 4;
     hipError_t err = hipSuccess;
     bool ok = false;
 #define ARGUS_FH(DD, HH)                                                                   \
     if (D == DD && fa.h == HH) {                                                           \
-        size_t lds = FitLds8<DD, HH>::bytes(fa.nplanes);                                   \
-        err = hipFuncSetAttribute((const void *)fit_accum8_kernel<DD, HH, PREC, NW, NW>,   \
+        size_t lds = FitLds8<DD, HH>::bytes(NWM);                                          \
+        err = hipFuncSetAttribute((const void *)fit_accum8_kernel<DD, HH, PREC, NWC, NWM>, \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (err == hipSuccess)                                                             \
-            hipLaunchKernelGGL((fit_accum8_kernel<DD, HH, PREC, NW, NW>), grid,            \
-                               dim3(64 * 2 * NW), lds, ctx->stream, fa);                   \
+            hipLaunchKernelGGL((fit_accum8_kernel<DD, HH, PREC, NWC, NWM>), grid,          \
+                               dim3(64 * (NWC + NWM)), lds, ctx->stream, fa);              \
         ok = true;                                                                         \
     }
 #define ARGUS_FD(DD)                                                                       \

@@ -21,6 +21,7 @@
 //   colf [32][32]                : alpha_k exp(-v^2/2s^2) v^j, index v+h
 //   gam  [32]                    : C'_k = conv_k + gam_k C'_0
 //   kpl  [32] (int)              : plane of basis k
+//   ipow [ARGUS_MAX_PLANES] (int): x-power i of plane p (filter parity)
 //   b2d  [32][31*31] (double)    : normalised 2-D basis B_k[v+h][u+h]
 struct BasisTables {
     float rowf[ARGUS_MAX_PLANES][32];
@@ -28,6 +29,7 @@ struct BasisTables {
     float gam[32];
     int32_t kpl[32];
     int32_t nb, nplanes, h, pad;
+    int32_t ipow[ARGUS_MAX_PLANES];    // x-power i of each row-filter plane
     double b2d[32][31 * 31];
 };
 
@@ -49,6 +51,7 @@ struct argus_ctx {
     std::vector<Timed> times;
     std::vector<hipEvent_t> ev_pool;
     hipEvent_t ev_open = nullptr;
+    int n_cu = 0;                      // compute units of the device
 };
 
 // ---- helpers implemented in argus.hip --------------------------------------

@@ -100,6 +100,7 @@ __global__ void basis_tables_kernel(argus_kernel_spec s, BasisTables *T) {
         for (int g = 0; g < s.n_gauss; ++g)
             for (int i = 0; i <= s.degree[g]; ++i, ++pp)
                 if (pp == p) {
+                    T->ipow[p] = i;
                     double is2 = 1.0 / (2.0 * s.sigma[g] * s.sigma[g]);
                     for (int u = -h; u <= h; ++u)
                         T->rowf[p][u + h] = (float)(exp(-(double)(u * u) * is2) * pow((double)u, i));
@@ -369,16 +370,26 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
     fa.h = spec->half_width;
     fa.nb = argus_nbasis(spec);
     fa.nplanes = argus_nplanes(spec);
-    // planes to waves, longest first onto the least loaded wave; a plane costs
-    // its row filter plus one column filter per basis function it feeds
+    // planes to the convolution waves, longest first onto the least loaded
+    // wave: 8 waves (wave 0 at most 1 plane, the others at most 2) or 4 waves
+    // (at most 4 each); at most 13 planes fit the basis limit.  Cost of a plane in VALU operations per pixel
+    // row with paired symmetric taps: its row filter (h + 1), the paired
+    // window of its column (2h, or h when it feeds one even filter) and h + 2
+    // per column filter it feeds; wave 0 also stages the fit-set weights.
     {
-        int cost[ARGUS_MAX_PLANES], load[4] = {0, 0, 0, 0}, nin[4] = {0, 0, 0, 0};
+        const int h = spec->half_width;
+        int cost[ARGUS_MAX_PLANES];
         int p = 0;
         for (int g = 0; g < spec->n_gauss; ++g)
-            for (int i = 0; i <= spec->degree[g]; ++i, ++p) cost[p] = 1 + (spec->degree[g] - i + 1);
+            for (int i = 0; i <= spec->degree[g]; ++i, ++p) {
+                const int nk = spec->degree[g] - i + 1;
+                cost[p] = (h + 1) + (nk > 1 ? 2 * h : h) + nk * (h + 2);
+            }
+        // 4 convolution waves (FP64, BF16x3 forms), up to 4 planes each
+        int load[4] = {3 * h, 0, 0, 0}, nin[4] = {};
+        bool used[ARGUS_MAX_PLANES] = {};
         for (int w = 0; w < 4; ++w)
             for (int j = 0; j < 4; ++j) fa.plist[w][j] = -1;
-        bool used[ARGUS_MAX_PLANES] = {};
         for (int n = 0; n < fa.nplanes; ++n) {
             int best = -1;
             for (int q = 0; q < fa.nplanes; ++q)
@@ -390,8 +401,9 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
             fa.plist[w][nin[w]++] = (int8_t)best;
             load[w] += cost[best];
         }
-        // the same for 8 convolution waves of at most 2 planes each
+        // 8 convolution waves (FP32 form)
         int load8[8] = {}, nin8[8] = {};
+        load8[0] = 3 * h;
         bool used8[ARGUS_MAX_PLANES] = {};
         for (int w = 0; w < 8; ++w)
             for (int j = 0; j < 2; ++j) fa.plist8[w][j] = -1;
@@ -401,7 +413,7 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
                 if (!used8[q] && (best < 0 || cost[q] > cost[best])) best = q;
             int w = -1;
             for (int c = 0; c < 8; ++c)
-                if (nin8[c] < 2 && (w < 0 || load8[c] < load8[w])) w = c;
+                if (nin8[c] < (c == 0 ? 1 : 2) && (w < 0 || load8[c] < load8[w])) w = c;
             used8[best] = true;
             fa.plist8[w][nin8[w]++] = (int8_t)best;
             load8[w] += cost[best];
@@ -413,11 +425,26 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
     int maxw = (d.width + fa.RX - 1) / fa.RX;
     int maxh = (d.height + fa.RY - 1) / fa.RY;
     fa.spt = (maxw + SW - 1) / SW;
-    // enough workgroups to fill the chip, without row chunks shorter than 8h
-    int base = fa.RX * fa.RY * fa.spt;
-    int want = (2048 + base - 1) / base;
-    int maxc = maxh / (8 * fa.h) > 1 ? maxh / (8 * fa.h) : 1;
-    fa.rchunks = want < 1 ? 1 : (want > maxc ? maxc : want);
+    // Row chunks: one workgroup runs per CU at a time, so the accumulation
+    // takes ceil(workgroups / CUs) rounds of (rows per chunk + 2h halo rows)
+    // steps each.  Take the chunk count (chunks no shorter than 8h) with the
+    // shortest such makespan, which also avoids a last round that leaves
+    // most CUs idle.
+    {
+        const int base = fa.RX * fa.RY * fa.spt;
+        const int maxc = maxh / (8 * fa.h) > 1 ? maxh / (8 * fa.h) : 1;
+        const int ncu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+        int64_t best = -1;
+        fa.rchunks = 1;
+        for (int c = 1; c <= maxc; ++c) {
+            const int64_t rounds = ((int64_t)base * c + ncu - 1) / ncu;
+            const int64_t t = rounds * ((maxh + c - 1) / c + 2 * fa.h);
+            if (best < 0 || t < best) {
+                best = t;
+                fa.rchunks = c;
+            }
+        }
+    }
     fa.sx = d.width > 1 ? 2.0 / (d.width - 1) : 0.0;
     fa.sy = d.height > 1 ? 2.0 / (d.height - 1) : 0.0;
     const int n_regions = fa.RX * fa.RY;
