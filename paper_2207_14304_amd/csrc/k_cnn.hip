@@ -31,6 +31,7 @@ struct argus_cnn {
     bf16 *wb[4] = {}, *wt[4] = {};             // forward and transposed-flipped copies
     bf16 *act[4] = {}, *dz[2] = {};            // activations, two dZ ping-pong buffers
     float *q = nullptr, *out = nullptr;         // per tile pooled features and outputs
+    float *pool = nullptr, *dq = nullptr;       // per stamp pooled features, per tile dq
     float *part = nullptr;                      // per tile gradient partials
     double *loss_part = nullptr;
     int step = 0;
@@ -142,14 +143,18 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradients: one workgroup per tile (its S stamps form the k range).
-// dW[o][tap][c] = sum_p dZ[p][o] A_in[p + off(tap)][c]; db[o] = sum_p dZ[p][o].
-// K steps are image rows (32 columns, the last one zero).
+// Weight gradients: G workgroups per tile, workgroup g taking stamps g,
+// g + G, ... of its tile (the k range).  dW[o][tap][c] = sum_p dZ[p][o]
+// A_in[p + off(tap)][c]; db[o] = sum_p dZ[p][o].  K steps are image rows
+// (32 columns, the last one zero).  The T G partials are summed afterwards in
+// a fixed order.
+constexpr int WG_GROUPS = 8;
+
 struct WgradArgs {
     const bf16 *dz, *ain;
     const uint8_t *valid;
-    float *part;                                // [tiles][32 * 9 * CIN + 32]
-    int S, npx;
+    float *part;                                // [tiles * G][32 * 9 * CIN + 32]
+    int S, npx, G;
 };
 
 template <int CIN>
@@ -186,7 +191,8 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
     bf16 *dzl = sm;                             // [32][31][32]   channel-first dZ
     bf16 *al = sm + 32 * W * DW;                // [CIN][33][40]  channel-first input
     __shared__ float dbp[NT];
-    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x, t = b / a.G, gi = b % a.G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, g = lane >> 4;
     constexpr int NMAX = (NTL + 3) / 4;
     floatx4 acc[2][NMAX];
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
     for (int i = tid; i < 32 * W * DW; i += NT) dzl[i] = (bf16)0.f;
     for (int i = tid; i < CIN * AH * AW; i += NT) al[i] = (bf16)0.f;
     __syncthreads();
-    for (int s = 0; s < a.S; ++s) {
+    for (int s = gi; s < a.S; s += a.G) {
         const int n = t * a.S + s;
         if (!a.valid[n]) continue;                       // uniform across the block
         const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
         }
         __syncthreads();
     }
-    float *part = a.part + (size_t)t * (32 * NJ + 32);
+    float *part = a.part + (size_t)b * (32 * NJ + 32);
 #pragma unroll
     for (int jj = 0; jj < NMAX; ++jj) {
         const int nt = wave + 4 * jj;
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Pooling and head.  One workgroup per tile.
+// Pooling (one workgroup per stamp) and head (one per tile).
 struct HeadArgs {
     const bf16 *a4;
     const uint8_t *valid;
@@ -278,34 +284,59 @@ struct HeadArgs {
     bf16 *dz4;
     float *part;                                // head gradient partials [tiles][nout*32 + nout]
     double *loss_part;
+    float *pool, *dq;                           // per stamp pooled features, per tile dq
     int S, npx, nout, T;
 };
 
-__global__ __launch_bounds__(NT) void cnn_head_fwd_kernel(HeadArgs a) {
-    __shared__ float red[8][32];
-    __shared__ float qs[32];
-    const int t = blockIdx.x, tid = threadIdx.x, c = tid & 31, part = tid >> 5;
-    float qsum = 0.f;
-    int nv = 0;
-    for (int s = 0; s < a.S; ++s) {
-        const int n = t * a.S + s;
-        if (!a.valid[n]) continue;
-        ++nv;
-        const bf16 *src = a.a4 + (size_t)n * a.npx * 32;
-        float sum = 0.f;
-        for (int p = part; p < a.npx; p += 8) sum += bf2f(src[(size_t)p * 32 + c]);
-        red[part][c] = sum;
-        __syncthreads();
-        if (part == 0) {
-            float tot = 0.f;
-            for (int i = 0; i < 8; ++i) tot += red[i][c];
-            qsum += tot / (float)a.npx;
-        }
-        __syncthreads();
+// Spatial mean of the last activation, one workgroup per stamp: a thread
+// sums 8 channels (one 16-byte load) of every 64th pixel; 64 threads share a
+// channel group and are summed through LDS.  Invalid stamps get zeros.
+__global__ __launch_bounds__(NT) void cnn_pool_kernel(HeadArgs a) {
+    __shared__ float red[NT][9];
+    const int n = blockIdx.x, tid = threadIdx.x;
+    if (!a.valid[n]) {
+        if (tid < 32) a.pool[(size_t)n * 32 + tid] = 0.f;
+        return;
     }
-    if (part == 0) qs[c] = nv > 0 ? qsum / (float)nv : 0.f;
+    const uint4 *src = (const uint4 *)(a.a4 + (size_t)n * a.npx * 32);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int i = tid; i < a.npx * 4; i += NT) {
+        const uint4 v = src[i];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            acc[2 * e] += __uint_as_float(w[e] << 16);
+            acc[2 * e + 1] += __uint_as_float(w[e] & 0xffff0000u);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[tid][e] = acc[e];
     __syncthreads();
-    if (tid < 32) a.q[t * 32 + tid] = qs[tid];
+    if (tid < 32) {
+        const int g = tid >> 3, e = tid & 7;          // channel tid = 8 g + e
+        float sum = 0.f;
+        for (int j = g; j < NT; j += 4) sum += red[j][e];
+        a.pool[(size_t)n * 32 + tid] = sum / (float)a.npx;
+    }
+}
+
+// Per tile: mean of the pooled features over its valid stamps, linear head.
+__global__ void cnn_head_fwd_kernel(HeadArgs a) {
+    __shared__ float qs[32];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    if (tid < 32) {
+        float qsum = 0.f;
+        int nv = 0;
+        for (int s = 0; s < a.S; ++s) {
+            const int n = t * a.S + s;
+            if (!a.valid[n]) continue;
+            ++nv;
+            qsum += a.pool[(size_t)n * 32 + tid];
+        }
+        qs[tid] = nv > 0 ? qsum / (float)nv : 0.f;
+        a.q[t * 32 + tid] = qs[tid];
+    }
+    __syncthreads();
     if (tid < a.nout) {
         float o = a.hb[tid];
         for (int k = 0; k < 32; ++k) o += a.hw[tid * 32 + k] * qs[k];
@@ -313,12 +344,14 @@ __global__ __launch_bounds__(NT) void cnn_head_fwd_kernel(HeadArgs a) {
     }
 }
 
-__global__ __launch_bounds__(NT) void cnn_head_bwd_kernel(HeadArgs a) {
-    __shared__ float dout[64], dq[32];
+// Per tile: loss, head gradient partials and the gradient of the pooled
+// features, already divided by (valid stamps x pixels) for the spread below.
+__global__ void cnn_head_bwd_kernel(HeadArgs a) {
+    __shared__ float dout[64];
     __shared__ double lred[64];
     const int t = blockIdx.x, tid = threadIdx.x;
     const float scale = 2.0f / (float)(a.T * a.nout);
-    if (tid < 64) {
+    {
         double l = 0.0;
         float d = 0.f;
         if (tid < a.nout) {
@@ -336,24 +369,44 @@ __global__ __launch_bounds__(NT) void cnn_head_bwd_kernel(HeadArgs a) {
         a.loss_part[t] = l;
     }
     float *part = a.part + (size_t)t * (a.nout * 32 + a.nout);
-    for (int i = tid; i < a.nout * 32; i += NT) part[i] = dout[i / 32] * a.q[t * 32 + i % 32];
+    for (int i = tid; i < a.nout * 32; i += 64) part[i] = dout[i / 32] * a.q[t * 32 + i % 32];
     if (tid < a.nout) part[a.nout * 32 + tid] = dout[tid];
     if (tid < 32) {
+        int nv = 0;
+        for (int s = 0; s < a.S; ++s) nv += a.valid[t * a.S + s] != 0;
+        const float inv = nv > 0 ? 1.0f / ((float)nv * (float)a.npx) : 0.f;
         float s = 0.f;
         for (int j = 0; j < a.nout; ++j) s += a.hw[j * 32 + tid] * dout[j];
-        dq[tid] = s;
+        a.dq[t * 32 + tid] = s * inv;
     }
-    __syncthreads();
-    int nv = 0;
-    for (int s = 0; s < a.S; ++s) nv += a.valid[t * a.S + s] != 0;
-    const float inv = nv > 0 ? 1.0f / ((float)nv * (float)a.npx) : 0.f;
-    for (int s = 0; s < a.S; ++s) {
-        const int n = t * a.S + s;
-        if (!a.valid[n]) continue;
-        const bf16 *src = a.a4 + (size_t)n * a.npx * 32;
-        bf16 *dst = a.dz4 + (size_t)n * a.npx * 32;
-        for (int i = tid; i < a.npx * 32; i += NT)
-            dst[i] = (bf16)(bf2f(src[i]) > 0.f ? dq[i & 31] * inv : 0.f);
+}
+
+// dZ of the last layer, one workgroup per valid stamp: the pooled-feature
+// gradient gated by the ReLU of the forward activation, 8 channels per
+// 16-byte load and store.
+__global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a) {
+    const int n = blockIdx.x, tid = threadIdx.x;
+    if (!a.valid[n]) return;
+    const int t = n / a.S;
+    const int g = tid & 3;                       // channels 8g .. 8g+7 (NT is a multiple of 4)
+    float dq[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dq[e] = a.dq[t * 32 + 8 * g + e];
+    const uint4 *src = (const uint4 *)(a.a4 + (size_t)n * a.npx * 32);
+    uint4 *dst = (uint4 *)(a.dz4 + (size_t)n * a.npx * 32);
+    for (int i = tid; i < a.npx * 4; i += NT) {
+        const uint4 v = src[i];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float lo = __uint_as_float(w[e] << 16), hi = __uint_as_float(w[e] & 0xffff0000u);
+            const bf16 blo = (bf16)(lo > 0.f ? dq[2 * e] : 0.f);
+            const bf16 bhi = (bf16)(hi > 0.f ? dq[2 * e + 1] : 0.f);
+            o[e] = (uint32_t)__builtin_bit_cast(uint16_t, blo) |
+                   ((uint32_t)__builtin_bit_cast(uint16_t, bhi) << 16);
+        }
+        dst[i] = uint4{o[0], o[1], o[2], o[3]};
     }
 }
 
@@ -720,7 +773,7 @@ int wgrad_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
     size_t lds = WgradShape<CIN>::bytes();
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad_kernel<CIN>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T), dim3(NT), lds, ctx->stream, wa);
+    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T * wa.G), dim3(NT), lds, ctx->stream, wa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
@@ -754,7 +807,9 @@ int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t 
     ha.a4 = c->act[3]; ha.valid = valid; ha.hw = c->master + c->hw_off; ha.hb = c->master + c->hb_off;
     ha.target = nullptr; ha.q = c->q; ha.out = c->out; ha.dz4 = nullptr; ha.part = nullptr;
     ha.loss_part = nullptr; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
-    hipLaunchKernelGGL(cnn_head_fwd_kernel, dim3(T), dim3(NT), 0, ctx->stream, ha);
+    ha.pool = c->pool; ha.dq = c->dq;
+    hipLaunchKernelGGL(cnn_pool_kernel, dim3(T * c->S), dim3(NT), 0, ctx->stream, ha);
+    hipLaunchKernelGGL(cnn_head_fwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
@@ -875,8 +930,9 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     bytes += 4 * 32 * 288 * sizeof(bf16) * 2;                       // wb, wt
     bytes += (4 * A + 2 * A) * sizeof(bf16);                        // act, dz
     bytes += (size_t)max_tiles * (32 + c->nout) * sizeof(float);    // q, out
-    bytes += (size_t)max_tiles * part_stride * sizeof(float);
+    bytes += (size_t)max_tiles * WG_GROUPS * part_stride * sizeof(float);
     bytes += (size_t)max_tiles * sizeof(double) + 4096;
+    bytes += (N + max_tiles) * 32 * sizeof(float) + 512;            // pool, dq
     if (hipMalloc(&c->mem, bytes) != hipSuccess) {
         delete c;
         return argus_fail(ctx, ARGUS_ENOMEM, "cnn buffers (%zu bytes)", bytes);
@@ -895,8 +951,10 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     for (int l = 0; l < 2; ++l) c->dz[l] = (bf16 *)take(A * 2);
     c->q = (float *)take((size_t)max_tiles * 32 * 4);
     c->out = (float *)take((size_t)max_tiles * c->nout * 4);
-    c->part = (float *)take((size_t)max_tiles * part_stride * 4);
+    c->part = (float *)take((size_t)max_tiles * WG_GROUPS * part_stride * 4);
     c->loss_part = (double *)take((size_t)max_tiles * 8);
+    c->pool = (float *)take(N * 32 * 4);
+    c->dq = (float *)take((size_t)max_tiles * 32 * 4);
     if (hipMemsetAsync(c->mem, 0, 4 * c->P * sizeof(float) + 1024, ctx->stream) != hipSuccess) {
         (void)hipFree(c->mem);
         delete c;
@@ -964,7 +1022,9 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     ha.a4 = c->act[3]; ha.valid = valid; ha.hw = c->master + c->hw_off; ha.hb = c->master + c->hb_off;
     ha.target = target; ha.q = c->q; ha.out = c->out; ha.dz4 = c->dz[1]; ha.part = c->part;
     ha.loss_part = c->loss_part; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
-    hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3(T), dim3(NT), 0, ctx->stream, ha);
+    ha.pool = c->pool; ha.dq = c->dq;
+    hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
+    hipLaunchKernelGGL(cnn_dz4_kernel, dim3(T * c->S), dim3(NT), 0, ctx->stream, ha);
     const int hlen = c->nout * 32 + c->nout;
     hipLaunchKernelGGL(cnn_reduce_kernel, dim3((hlen + 255) / 256), dim3(256), 0, ctx->stream,
                        (const float *)c->part, hlen, hlen, T, c->grad + c->hw_off);
@@ -981,11 +1041,12 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
         wa.part = c->part;
         wa.S = c->S;
         wa.npx = c->npx;
+        wa.G = WG_GROUPS;
         rc = l == 0 ? wgrad_launch<2>(ctx, wa, T) : wgrad_launch<32>(ctx, wa, T);
         if (rc) return rc;
         const int len = 32 * 9 * c->cin[l] + 32;
         hipLaunchKernelGGL(cnn_reduce_kernel, dim3((len + 255) / 256), dim3(256), 0, ctx->stream,
-                           (const float *)c->part, len, len, T, c->grad + c->w_off[l]);
+                           (const float *)c->part, len, len, T * WG_GROUPS, c->grad + c->w_off[l]);
         ARGUS_HIP_CHECK(ctx, hipGetLastError());
         if (l > 0) {
             ConvArgs ca;

@@ -266,6 +266,47 @@ def test_fit_parity_noisy(ctx, D, h, tiles, prec):
     assert abs(gc2[0] / oc2[0] - 1) <= NOISY_CHI2_TOL[prec]
 
 
+def _jacobi_cond(planes, os_):
+    """Condition number of the Jacobi-scaled normal matrix (oracle, FP64)."""
+    from oracle import core
+    A = np.asarray(core.normal_equations(*planes, os_)[0])
+    A = A[0] if A.ndim == 3 else A
+    d = np.sqrt(np.diag(A))
+    ev = np.linalg.eigvalsh(A / np.outer(d, d))
+    return ev[-1] / ev[0]
+
+
+# Other basis layouts: four Gaussians with 13 row-filter planes (the most the
+# 31-basis limit allows; every convolution wave holds its full share of
+# planes) and a degree-6 Gaussian (one plane feeding 7 column filters).  The
+# stamp bar is the noisy-data bar of the standard basis scaled by the ratio
+# of the Jacobi-scaled condition numbers (first-order perturbation: the
+# solution error grows with the condition number for the same relative error
+# in the moments); the four-Gaussian layout is ~30x worse conditioned.
+@pytest.mark.parametrize("prec", [argus.FP32, argus.FP64])
+@pytest.mark.parametrize("sigmas,degrees", [((0.8, 1.6, 2.4, 3.5), (3, 3, 3, 0)),
+                                            ((1.2, 2.6), (6, 0))])
+def test_fit_parity_basis_layouts(ctx, sigmas, degrees, prec):
+    planes = _noisy_pair(300, 260, 91, n_stars=300)
+    spec = argus.make_spec(sigmas=sigmas, degrees=degrees, half_width=7, spatial_degree=1,
+                           bg_degree=1, precision=prec)
+    os_ = _ospec(spec)
+    co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+    oco, ost, onf = oracle.fit_kernel(*planes, os_)
+    assert st[0] == ost[0] == 0
+    assert nf[0] == onf[0]
+    o_stamps, _ = oracle.expand_kernel(oco, os_)
+    err = np.abs(stamps - o_stamps).max() / np.abs(o_stamps).max()
+    gc2 = oracle.chi2(*planes, os_, co)
+    oc2 = oracle.chi2(*planes, os_, oco)
+    std = _ospec(_spec(half_width=7, spatial_degree=1, bg_degree=1))
+    ratio = max(1.0, _jacobi_cond(planes, os_) / _jacobi_cond(planes, std))
+    print(f"{degrees} prec {prec}: stamp error {err:.3e}, condition ratio {ratio:.1f}, "
+          f"chi2 ratio - 1 {gc2[0] / oc2[0] - 1:.3e}")
+    assert err <= NOISY_STAMP_TOL[prec] * ratio
+    assert abs(gc2[0] / oc2[0] - 1) <= NOISY_CHI2_TOL[prec]
+
+
 def test_fit_per_tile_parity(ctx):
     planes = _noisy_pair(290, 260, 77, n_stars=400)
     spec = _spec(half_width=7, tiles_x=2, tiles_y=2, mode=argus.FIT_PER_TILE)
