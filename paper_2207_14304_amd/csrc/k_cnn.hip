@@ -454,7 +454,7 @@ __global__ void cnn_pack_kernel(const float *w, int cin, int kp, bf16 *wb, bf16 
 }
 
 // ---------------------------------------------------------------------------
-// Stamp extraction: one workgroup per tile.  Candidates are positive
+// Stamp extraction: one workgroup of NTS threads per tile.  Candidates are positive
 // reference local maxima (strictly above earlier 8-neighbours in raster
 // order, >= later ones) whose stamp lies inside the frame and whose peak
 // stands snr_min noise sigmas above the tile's sky (the median of its
@@ -469,6 +469,8 @@ __global__ void cnn_pack_kernel(const float *w, int cin, int kp, bf16 *wb, bf16 
 // float bit patterns (positive floats order like their bits; 4096 buckets
 // of 1/8 octave) picks the lowest bucket whose suffix count fits, so every
 // retained candidate is brighter than every dropped one.
+constexpr int NTS = 1024;      // threads of the stamp extraction workgroup
+constexpr int WW = 8;          // its waves that walk the ranking (LDS stamp slots)
 constexpr int MAXC = 2048;
 constexpr int NBUCKET = 4096;
 // inputs near unit size: a unit-sum 31x31 stamp has values of order 1e-3,
@@ -543,9 +545,9 @@ __device__ uint32_t tile_select(const StampArgs &a, int x0, int y0, int tw, int 
     __shared__ int s_digit, s_k;
     if (tid == 0) s_k = k;
     for (int shift = 24; shift >= 0; shift -= 8) {
-        bins[tid] = 0;
+        if (tid < 256) bins[tid] = 0;
         __syncthreads();
-        for (int i = tid; i < npix; i += NT) {
+        for (int i = tid; i < npix; i += NTS) {
             const int64_t o = (int64_t)(y0 + i / tw) * P + x0 + i % tw;
             if (a.rmask[o] != 0) continue;
             const uint32_t key = fkey(a.ref[o]);
@@ -566,16 +568,16 @@ __device__ uint32_t tile_select(const StampArgs &a, int x0, int y0, int tw, int 
     return prefix;
 }
 
-__global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
+__global__ __launch_bounds__(NTS) void stamps_kernel(StampArgs a) {
     __shared__ unsigned long long keys[MAXC];
     __shared__ int hist[NBUCKET];
-    __shared__ int psum[NT];
+    __shared__ int psum[NTS];
     __shared__ int ncand, nacc, cutoff, dropped;
-    __shared__ int flag[4];
-    __shared__ float fmed[4];
+    __shared__ int flag[WW];
+    __shared__ float fmed[WW];
     __shared__ int acc_y[64], acc_x[64];
     __shared__ float acc_m[64];
-    extern __shared__ __align__(16) float sst[];   // per wave: 2 stamps + 256 sort slots
+    extern __shared__ __align__(16) float sst[];   // per walking wave: 2 stamps + 256 sort slots
     const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tx = t % a.TX, ty = t / a.TX;
     const int x0 = (int)((int64_t)tx * a.W / a.TX), x1 = (int)((int64_t)(tx + 1) * a.W / a.TX);
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
     __syncthreads();
     {
         int cnt = 0;
-        for (int i = tid; i < npix; i += NT)
+        for (int i = tid; i < npix; i += NTS)
             cnt += a.rmask[(int64_t)(y0 + i / tw) * P + x0 + i % tw] == 0;
         atomicAdd(&s_nun, cnt);
     }
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
             sky = (v1 + v2) * 0.5f;
         }
     }
-    for (int i = tid; i < NBUCKET; i += NT) hist[i] = 0;
+    for (int i = tid; i < NBUCKET; i += NTS) hist[i] = 0;
     if (tid == 0) { ncand = 0; nacc = 0; }
     __syncthreads();
     // candidate test; the stamp-in-frame bound keeps every neighbour in the frame
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
         const float vv = a.rvar[o];
         return vv > 0.f && (c - sky) / sqrtf(vv) >= a.snr_min;
     };
-    for (int i = tid; i < npix; i += NT) {
+    for (int i = tid; i < npix; i += NTS) {
         float c;
         if (is_cand(y0 + i / tw, x0 + i % tw, c)) atomicAdd(&hist[__float_as_uint(c) >> 20], 1);
     }
@@ -630,16 +632,16 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
     // lowest bucket whose suffix count fits in MAXC
     {
         int sum = 0;
-        for (int b = 0; b < NBUCKET / NT; ++b) sum += hist[tid * (NBUCKET / NT) + b];
+        for (int b = 0; b < NBUCKET / NTS; ++b) sum += hist[tid * (NBUCKET / NTS) + b];
         psum[tid] = sum;
     }
     __syncthreads();
     if (tid == 0) {
-        constexpr int CH = NBUCKET / NT;
+        constexpr int CH = NBUCKET / NTS;
         int tot = 0;
-        for (int i = 0; i < NT; ++i) tot += psum[i];
+        for (int i = 0; i < NTS; ++i) tot += psum[i];
         int acc = 0, cut = NBUCKET;                 // buckets >= cut are kept
-        int i = NT - 1;
+        int i = NTS - 1;
         while (i >= 0 && acc + psum[i] <= MAXC) {   // whole chunks from the top
             acc += psum[i];
             cut = i * CH;
@@ -656,7 +658,7 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
         dropped = tot - acc;
     }
     __syncthreads();
-    for (int i = tid; i < npix; i += NT) {
+    for (int i = tid; i < npix; i += NTS) {
         const int y = y0 + i / tw, x = x0 + i % tw;
         float c;
         if (is_cand(y, x, c) && (int)(__float_as_uint(c) >> 20) >= cutoff) {
@@ -670,11 +672,11 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
     const int nc = ncand;
     int m2 = 1;
     while (m2 < nc) m2 <<= 1;
-    for (int i = nc + tid; i < m2; i += NT) keys[i] = ~0ull;
+    for (int i = nc + tid; i < m2; i += NTS) keys[i] = ~0ull;
     __syncthreads();
     for (int k = 2; k <= m2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < m2; i += NT) {
+            for (int i = tid; i < m2; i += NTS) {
                 const int p = i ^ j;
                 if (p > i) {
                     const bool up = (i & k) == 0;
@@ -685,14 +687,14 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
             __syncthreads();
         }
     }
-    // walk the ranking four candidates at a time, one per wave
-    float *ws = sst + (size_t)wave * (2 * npx + 256);
-    for (int k0 = 0; k0 < nc; k0 += 4) {
+    // walk the ranking WW candidates at a time, one per walking wave
+    float *ws = sst + (size_t)(wave < WW ? wave : 0) * (2 * npx + 256);
+    for (int k0 = 0; k0 < nc; k0 += WW) {
         if (nacc >= a.S) break;                 // uniform: shared, read after a barrier
         const int k = k0 + wave;
         int ok = 0;
         float med = 0.f;
-        if (k < nc) {
+        if (wave < WW && k < nc) {
             const unsigned int idx = (unsigned int)(keys[k] & 0xFFFFFFFFull);
             const int y = idx / a.W, x = idx % a.W;
             int bad = 0;
@@ -710,10 +712,10 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
                 ok = vv > 0.f && (v - med) / sqrtf(vv) >= a.snr_min;
             }
         }
-        if (lane == 0) { flag[wave] = ok; fmed[wave] = med; }
+        if (lane == 0 && wave < WW) { flag[wave] = ok; fmed[wave] = med; }
         __syncthreads();
         if (tid == 0) {
-            for (int w = 0; w < 4 && nacc < a.S; ++w) {
+            for (int w = 0; w < WW && nacc < a.S; ++w) {
                 if (!flag[w]) continue;
                 const unsigned int idx = (unsigned int)(keys[k0 + w] & 0xFFFFFFFFull);
                 acc_y[nacc] = idx / a.W;
@@ -725,8 +727,8 @@ __global__ __launch_bounds__(NT) void stamps_kernel(StampArgs a) {
         __syncthreads();
     }
     if (tid == 0 && nacc < a.S && dropped > 0) atomicAdd(a.overflow, 1);
-    // stamps: one wave per kept stamp
-    for (int s = wave; s < a.S; s += 4) {
+    // stamps: one walking wave per kept stamp
+    for (int s = wave; s < a.S && wave < WW; s += WW) {
         const int64_t base = ((int64_t)t * a.S + s) * npx * 2;
         uint8_t ok = 0;
         if (s < nacc) {
@@ -1096,10 +1098,10 @@ int argus_extract_stamps(argus_ctx *ctx, argus_dims d, const float *ref, const f
     a.pitch = d.pitch; a.W = d.width; a.H = d.height; a.TX = tiles_x; a.TY = tiles_y;
     a.S = stamps_per_tile; a.r = half; a.snr_min = snr_min;
     const int npx = (2 * half + 1) * (2 * half + 1);
-    size_t lds = (size_t)4 * (2 * npx + 256) * sizeof(float);
+    size_t lds = (size_t)WW * (2 * npx + 256) * sizeof(float);
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)stamps_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(stamps_kernel, dim3(tiles_x * tiles_y), dim3(NT), lds, ctx->stream, a);
+    hipLaunchKernelGGL(stamps_kernel, dim3(tiles_x * tiles_y), dim3(NTS), lds, ctx->stream, a);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
