@@ -75,6 +75,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that decide the frame fit's memory traffic (kernel and its launch).
+FIT_SOURCES = ["paper_2207_14304_amd/csrc/fit_accum8.h", "paper_2207_14304_amd/csrc/fit_accum.h",
+               "paper_2207_14304_amd/csrc/k_fit_fp32.hip", "paper_2207_14304_amd/csrc/k_fit.hip"]
+TRAFFIC_FILE = "profiles/fit_accum_traffic.md"
+
+
+def fit_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FIT_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the frame fit from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the same
+    counter on a plain 1 GiB copy kernel), or None when the kernel sources
+    have changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("source_sha256") != fit_source_hash():
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def algorithmic_work(name, spec, npix, n_ref):
     """(kind, amount per launch) of the algorithmic work of an internal kernel."""
     D = spec.spatial_degree
@@ -372,7 +409,8 @@ def main():
         peak = PEAK_FP32_VALU_TFLOPS if kind == "alu" else PEAK_FP32_MFMA_TFLOPS
         unit = "TFLOP/s"
     roof = {"bound": kind, "kernel": dom, "achieved": round(ach, 2), "peak": peak, "unit": unit,
-            "frac": round(ach / peak, 4), "traffic": None}
+            "frac": round(ach / peak, 4),
+            "traffic": measured_traffic() if dom == "fit_accum" else None}
 
     cpu = None
     if not args.no_cpu_baseline:

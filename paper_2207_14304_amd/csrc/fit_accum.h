@@ -216,8 +216,12 @@ struct WaveGram {
     // p = 16 pk + s (FP32, FP64) or p = 32 s + 8 pk + e (BF16X3), so a lane's
     // operands of consecutive steps are contiguous and load 16 bytes at once.
     static constexpr int CKM = SW + 4;
-    __device__ void row_km(const float *cvec, const float *wx, const double *wxd,
-                           const double *ypw, int lane, float g0, float g1) {
+    // Accumulator of one task: 4 FP32 (FP64 for ARGUS_FP64) values per lane.
+    using Acc = typename std::conditional<PREC == ARGUS_FP64, doublex4, floatx4>::type;
+
+    // The moments of one row into acc (not yet flushed into the FP64 sums).
+    __device__ void row_km_acc(const float *cvec, const float *wx, const double *wxd, int lane,
+                               float g0, float g1, Acc (&acc)[NTW > 0 ? NTW : 1]) {
         if constexpr (NTW > 0) {
             const int col = lane & 15, pk = lane >> 4;
             if constexpr (PREC == ARGUS_FP32 || PREC == ARGUS_FP64) {
@@ -226,7 +230,6 @@ struct WaveGram {
                 const float *pa = cvec + col * CKM + 16 * pk;
                 const float *pb = cvec + (16 + col) * CKM + 16 * pk;
                 const float *pz = cvec + 16 * pk;
-                TV acc[NTW];
 #pragma unroll
                 for (int j = 0; j < NTW; ++j) acc[j] = TV{0, 0, 0, 0};
                 // the operands of 4 steps are loaded while the 4 steps before run
@@ -287,9 +290,7 @@ struct WaveGram {
                         }
                     }
                 }
-                flush(acc, ypw);
             } else {
-                floatx4 acc[NTW];
 #pragma unroll
                 for (int j = 0; j < NTW; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -340,9 +341,15 @@ struct WaveGram {
                         acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
                     }
                 }
-                flush(acc, ypw);
             }
         }
+    }
+
+    __device__ void row_km(const float *cvec, const float *wx, const double *wxd,
+                           const double *ypw, int lane, float g0, float g1) {
+        Acc acc[NTW > 0 ? NTW : 1];
+        row_km_acc(cvec, wx, wxd, lane, g0, g1, acc);
+        flush(acc, ypw);
     }
 
     // Output element of register r in this lane: column lane % 16; row

@@ -317,9 +317,25 @@ __device__ void fit_mfma8(const FitArgs &a, float *lds, int sx_begin, int sx_end
     L l(lds);
     double *rhsbuf = (double *)lds;
 
-    WaveGram<D, MW, PREC, NWM> gram;
+    using G = WaveGram<D, MW, PREC, NWM>;
+    G gram;
     double RF[S::NR];
     gram.zero();
+    // Of the two MFMA waves on a SIMD (MW and MW + NWM/2), the second flushes
+    // a row's moments at the start of the next step, before its right-hand
+    // side and MFMAs: its VALU work then overlaps its partner's MFMAs (and
+    // the other way round) instead of both waves using the matrix pipe and
+    // the VALU at the same times.
+    constexpr bool DEFER = NWM == 8 && MW >= NWM / 2;
+    typename G::Acc acc[G::NTW > 0 ? G::NTW : 1];
+    bool have = false;
+    int yprev = 0;
+    auto ypowers = [&](int yv, double *ypw) {
+        const double yt = (double)yv * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
+        double yp = 1.0;
+#pragma unroll
+        for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
+    };
 #pragma unroll
     for (int i = 0; i < S::NR; ++i) RF[i] = 0.0;
     const float g0 = (lane & 15) < a.nb ? a.tab->gam[lane & 15] : 0.f;
@@ -338,13 +354,14 @@ __device__ void fit_mfma8(const FitArgs &a, float *lds, int sx_begin, int sx_end
             if (yy - 1 >= ry0 + HH && yy - 1 < yend) {
                 const int pb = buf ^ 1;
                 double ypw[2 * D + 1];
-                {
-                    const double yt = (double)y * a.sy - (a.sy != 0.0 ? 1.0 : 0.0);
-                    double yp = 1.0;
-#pragma unroll
-                    for (int b = 0; b <= 2 * D; ++b) { ypw[b] = yp; yp *= yt; }
+                if constexpr (DEFER) {
+                    if (have) {
+                        ypowers(yprev, ypw);
+                        gram.flush(acc, ypw);
+                    }
                 }
-                gram.row_km(l.cvec(pb), l.wx(pb), l.wxd(pb), ypw, lane, g0, g1);
+                ypowers(y, ypw);
+                if constexpr (!DEFER) gram.row_km(l.cvec(pb), l.wx(pb), l.wxd(pb), ypw, lane, g0, g1);
                 const float *cv = l.cvec(pb);
                 const int k = lane & 31, half = lane >> 5;
                 if constexpr (PREC == ARGUS_FP64) {
@@ -380,8 +397,20 @@ __device__ void fit_mfma8(const FitArgs &a, float *lds, int sx_begin, int sx_end
                         for (int b = 0; b <= D; ++b)
                             if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
                 }
+                if constexpr (DEFER) {
+                    gram.row_km_acc(l.cvec(pb), l.wx(pb), l.wxd(pb), lane, g0, g1, acc);
+                    have = true;
+                    yprev = y;
+                }
             }
             __syncthreads();
+        }
+    }
+    if constexpr (DEFER) {
+        if (have) {
+            double ypw[2 * D + 1];
+            ypowers(yprev, ypw);
+            gram.flush(acc, ypw);
         }
     }
     // partials: moments, rhs pieces through LDS (summed by the whole workgroup)
