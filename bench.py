@@ -2,7 +2,7 @@
 
 One step is the whole path over one synthetic full IMX455 frame pair
 (9576 x 6388 uint16): calibrate the 5 reference frames and coadd them with a
-3-sigma clip, calibrate the science frame, fit the spatially varying kernel
+3-sigma clip (one fused kernel), calibrate the science frame, fit the spatially varying kernel
 (21x21, 31 Gaussian bases, degree-2 polynomial, 16x16 sub-tile partials,
 192 unknowns), expand it, convolve-subtract, and detect.  Inputs (raw frames
 and calibration masters) are resident in HBM before the timed region.
@@ -120,6 +120,8 @@ def algorithmic_work(name, spec, npix, n_ref):
         return "hbm", 20.0 * npix                    # u16 + 2 f32 + u8 in, 2 f32 + u8 out
     if name == "coadd":
         return "hbm", (9.0 * n_ref + 10.0) * npix    # n x (2 f32 + u8) in, 2 f32 + 2 u8 out
+    if name == "calibrate_coadd":
+        return "hbm", (2.0 * n_ref + 19.0) * npix    # n u16 + 2 f32 + u8 in, 2 f32 + 2 u8 out
     if name == "detect_map":
         return "hbm", 14.0 * npix                    # 2 f32 + u8 in, f32 + u8 out
     if name == "subtract":
@@ -383,9 +385,10 @@ def main():
     npix = W * H
     log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {wall:.2f} s)")
 
-    names = ["calibrate", "coadd", "fit_accum", "fit_reduce", "fit_solve", "subtract",
-             "detect_map"]
+    names = ["calibrate", "calibrate_coadd", "fit_accum", "fit_reduce", "fit_solve",
+             "subtract", "detect_map"]
     kt = {n: float(ctx.kernel_time_ms(n)) for n in names}     # average over the timed launches
+    kt = {n: t for n, t in kt.items() if t >= 0}
     ctx.set_timing(False)
     log("kernel ms: " + json.dumps({k: round(v, 4) for k, v in kt.items()}))
     stages = {}

@@ -115,10 +115,10 @@ const char *argus_last_error(const argus_ctx *ctx);
 /* Per-kernel timing (for measurement only): while enabled, every launch of
  * an internal kernel is bracketed by HIP events on the context stream, with
  * no synchronisation.  argus_kernel_time_ms waits for the recorded launches
- * of the named kernel ("calibrate", "coadd", "fit_accum", "fit_reduce",
- * "fit_solve", "subtract", "detect_map", "batch") and returns their average device
- * time in ms, or -1 if none was recorded.  Enabling or disabling timing
- * discards the records. */
+ * of the named kernel ("calibrate", "coadd", "calibrate_coadd", "fit_accum",
+ * "fit_reduce", "fit_solve", "subtract", "detect_map", "batch") and returns
+ * their average device time in ms, or -1 if none was recorded.  Enabling or
+ * disabling timing discards the records. */
 int  argus_ctx_set_timing(argus_ctx *ctx, int enable);
 float argus_kernel_time_ms(argus_ctx *ctx, const char *kernel);
 
@@ -149,6 +149,23 @@ int argus_coadd(argus_ctx *ctx, argus_dims dims, int n_frames,
                 const float *const *cal, const float *const *var,
                 const uint8_t *const *mask, float kappa, int max_iter,
                 float *ref, float *ref_var, uint8_t *ref_mask, uint8_t *n_used);
+
+/* ---- fused calibration + reference coadd (Image Management; Deep
+ * Coaddition) --------------------------------------------------------------
+ * The n_frames (1..8) raw frames of one camera, which share dark, flat and
+ * bpm, are calibrated exactly as by argus_calibrate and coadded exactly as by
+ * argus_coadd (same gain, read_noise, sat_adu, kappa and max_iter rules),
+ * without writing the calibrated frames: only raw frames and masters are
+ * read and only ref, ref_var, ref_mask and n_used (nullable) are written.
+ * Results are bit-identical to argus_calibrate on each frame followed by
+ * argus_coadd.  raw is a HOST array of n_frames DEVICE pointers (u16, the
+ * dims' pitch).  Errors as for argus_calibrate and argus_coadd.  Streaming;
+ * HBM-bound. */
+int argus_calibrate_coadd(argus_ctx *ctx, argus_dims dims, int n_frames,
+                          const uint16_t *const *raw, const float *dark, const float *flat,
+                          const uint8_t *bpm, float gain, float read_noise, uint16_t sat_adu,
+                          float kappa, int max_iter, float *ref, float *ref_var,
+                          uint8_t *ref_mask, uint8_t *n_used);
 
 /* Number of unknowns per solve and number of solves for a spec. */
 int argus_kernel_dims(const argus_kernel_spec *spec, int *n_unknowns, int *n_solves);

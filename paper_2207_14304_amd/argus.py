@@ -24,6 +24,7 @@ FP32, BF16X3, FP64 = 0, 1, 2
 # every symbol declared in include/argus.h
 SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "argus_last_error",
            "argus_ctx_set_timing", "argus_kernel_time_ms", "argus_calibrate", "argus_coadd",
+           "argus_calibrate_coadd",
            "argus_kernel_dims", "argus_fit_kernel", "argus_expand_kernel", "argus_subtract",
            "argus_detect", "argus_batch_plan", "argus_batch_run", "argus_batch_info",
            "argus_batch_destroy", "argus_cnn_create", "argus_cnn_destroy",
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.argus_kernel_time_ms.restype = f32
     lib.argus_calibrate.argtypes = [vp, Dims, vp, vp, vp, vp, f32, f32, C.c_uint16, vp, vp, vp]
     lib.argus_coadd.argtypes = [vp, Dims, C.c_int, vp, vp, vp, f32, C.c_int, vp, vp, vp, vp]
+    lib.argus_calibrate_coadd.argtypes = [vp, Dims, C.c_int, vp, vp, vp, vp, f32, f32, C.c_uint16,
+                                          f32, C.c_int, vp, vp, vp, vp]
     lib.argus_kernel_dims.argtypes = [C.POINTER(KernelSpec), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 9
     lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
@@ -224,6 +227,18 @@ class Context:
             self.h, _dims(cals[0]), n, pc, pv, pm, float(kappa), int(max_iter),
             _ptr(ref, torch.float32), _ptr(ref_var, torch.float32), _ptr(ref_mask, torch.uint8),
             _ptr(n_used, torch.uint8)))
+
+    def calibrate_coadd(self, raws, dark, flat, bpm, gain, read_noise, sat_adu, kappa, max_iter,
+                        ref, ref_var, ref_mask, n_used=None):
+        torch = self._torch
+        self._bind()
+        n = len(raws)
+        pr = (C.c_void_p * n)(*[_ptr(r, torch.uint16) for r in raws])
+        self._check(self.lib.argus_calibrate_coadd(
+            self.h, _dims(raws[0]), n, pr, _ptr(dark, torch.float32), _ptr(flat, torch.float32),
+            _ptr(bpm, torch.uint8), float(gain), float(read_noise), int(sat_adu), float(kappa),
+            int(max_iter), _ptr(ref, torch.float32), _ptr(ref_var, torch.float32),
+            _ptr(ref_mask, torch.uint8), _ptr(n_used, torch.uint8)))
 
     def fit_kernel(self, spec, ref, ref_var, ref_mask, sci, sci_var, sci_mask, coeffs, n_fit,
                    status):

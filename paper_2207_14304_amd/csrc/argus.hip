@@ -187,6 +187,29 @@ int argus_coadd(argus_ctx *ctx, argus_dims dims, int n_frames, const float *cons
                         ref_mask, n_used);
 }
 
+int argus_calibrate_coadd(argus_ctx *ctx, argus_dims dims, int n_frames,
+                          const uint16_t *const *raw, const float *dark, const float *flat,
+                          const uint8_t *bpm, float gain, float read_noise, uint16_t sat_adu,
+                          float kappa, int max_iter, float *ref, float *ref_var,
+                          uint8_t *ref_mask, uint8_t *n_used) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (n_frames < 1 || n_frames > ARGUS_MAX_FRAMES)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate_coadd: n_frames %d not in 1..8", n_frames);
+    if (!raw || !dark || !flat || !ref || !ref_var || !ref_mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate_coadd: null pointer");
+    for (int i = 0; i < n_frames; ++i)
+        if (!raw[i]) return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate_coadd: null frame pointer %d", i);
+    if (!(gain > 0.f) || !(read_noise >= 0.f))
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate_coadd: gain must be > 0, read noise >= 0");
+    if (!(kappa > 0.f) || max_iter < 0 || max_iter > 64)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_calibrate_coadd: kappa > 0 and 0 <= max_iter <= 64");
+    return launch_calibrate_coadd(ctx, dims, n_frames, raw, dark, flat, bpm, gain, read_noise,
+                                  sat_adu, kappa, max_iter, ref, ref_var, ref_mask, n_used);
+}
+
 static int check_spec(argus_ctx *ctx, const argus_kernel_spec *s) {
     if (!s) return argus_fail(ctx, ARGUS_EINVAL, "null kernel spec");
     if (s->n_gauss < 1 || s->n_gauss > 4)

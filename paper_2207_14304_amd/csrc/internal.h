@@ -77,6 +77,10 @@ static inline int argus_nplanes(const argus_kernel_spec *s) {
 int launch_calibrate(argus_ctx *ctx, argus_dims d, const uint16_t *raw, const float *dark,
                      const float *flat, const uint8_t *bpm, float gain, float rn,
                      uint16_t sat, float *cal, float *var, uint8_t *mask);
+int launch_calibrate_coadd(argus_ctx *ctx, argus_dims d, int n, const uint16_t *const *raw,
+                           const float *dark, const float *flat, const uint8_t *bpm, float gain,
+                           float rn, uint16_t sat, float kappa, int max_iter, float *ref,
+                           float *ref_var, uint8_t *ref_mask, uint8_t *n_used);
 int launch_coadd(argus_ctx *ctx, argus_dims d, int n, const float *const *cal,
                  const float *const *var, const uint8_t *const *mask, float kappa,
                  int max_iter, float *ref, float *ref_var, uint8_t *ref_mask,

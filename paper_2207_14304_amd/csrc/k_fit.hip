@@ -165,14 +165,28 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
-__global__ __launch_bounds__(NTHR) void fit_solve_kernel(SolveArgs a) {
+constexpr int SOLVE_THREADS = 1024;
+
+// One workgroup of SOLVE_THREADS per solve.  Rows of the packed triangle are
+// addressed through a table of row offsets; a wave walks a row with its
+// lanes on consecutive columns (contiguous in the packed storage).  The
+// factorisation takes one barrier per column: step j updates the trailing
+// matrix with the unscaled column j (a_ic -= a_ij a_cj / a_jj) and scales
+// column j - 1, which no thread reads during step j.
+__global__ __launch_bounds__(SOLVE_THREADS) void fit_solve_kernel(SolveArgs a) {
+    constexpr int NT = SOLVE_THREADS, NWV = NT / 64;
     extern __shared__ double sl[];
+    __shared__ int roff[256];             // r (r + 1) / 2 for r < n <= 192
+    __shared__ short rk[256];             // basis, x-power and y-power of row r
+    __shared__ unsigned char rp[256], rq[256];
+    __shared__ double rdiag[256];         // 1 / L_ii
     const int n = a.n, tid = threadIdx.x, sol = blockIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int ntri = n * (n + 1) / 2;
     double *L = a.gtri ? a.gtri + (size_t)sol * ntri : sl;
     double *bb = sl + (a.gtri ? 0 : ntri);
     double *dd = bb + n;
-    double *red = dd + n;                 // [8]
+    double *red = dd + n;                 // [NWV]
     __shared__ int bad;
     const double *sums = a.sums + (size_t)sol * a.stride;
     const int D = a.D, NQ = (2 * D + 1) * (2 * D + 2) / 2;
@@ -183,79 +197,84 @@ __global__ __launch_bounds__(NTHR) void fit_solve_kernel(SolveArgs a) {
         if (a.n_fit) a.n_fit[sol] = (int64_t)cnt;
     }
     if (cnt < (double)n) {
-        for (int i = tid; i < n; i += NTHR) co[i] = __builtin_nan("");
+        for (int i = tid; i < n; i += NT) co[i] = __builtin_nan("");
         if (tid == 0) a.status[sol] = ARGUS_ETOOFEW;
         return;
     }
-    // assemble packed lower triangle and rhs
-    for (int idx = tid; idx < ntri; idx += NTHR) {
-        int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-        while ((r + 1) * (r + 2) / 2 <= idx) ++r;
-        while (r * (r + 1) / 2 > idx) --r;
-        int c = idx - r * (r + 1) / 2;
-        int kr, pr, qr, kc, pc, qc;
-        unpack_row(r, a.nb, D, a.Dbg, kr, pr, qr);
-        unpack_row(c, a.nb, D, a.Dbg, kc, pc, qc);
-        L[idx] = gram_at(sums, qidx(pr + pc, qr + qc, 2 * D), kr, kc);
-    }
-    for (int r = tid; r < n; r += NTHR) {
+    for (int r = tid; r < n; r += NT) {
         int k, p, q;
         unpack_row(r, a.nb, D, a.Dbg, k, p, q);
-        bb[r] = sums[(size_t)NQ * 768 + qidx(p, q, D) * 32 + k];
+        roff[r] = r * (r + 1) / 2;
+        rk[r] = (short)k;
+        rp[r] = (unsigned char)p;
+        rq[r] = (unsigned char)q;
     }
     __syncthreads();
-    for (int r = tid; r < n; r += NTHR) {
-        double dg = L[r * (r + 1) / 2 + r];
+    // assemble the packed lower triangle and the rhs
+    for (int r = wv; r < n; r += NWV) {
+        const int kr = rk[r], pr = rp[r], qr = rq[r];
+        for (int c = lane; c <= r; c += 64)
+            L[roff[r] + c] = gram_at(sums, qidx(pr + rp[c], qr + rq[c], 2 * D), kr, rk[c]);
+    }
+    for (int r = tid; r < n; r += NT) bb[r] = sums[(size_t)NQ * 768 + qidx(rp[r], rq[r], D) * 32 + rk[r]];
+    __syncthreads();
+    for (int r = tid; r < n; r += NT) {
+        double dg = L[roff[r] + r];
         if (!(dg > 0.0)) bad = 1;
         dd[r] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
     }
     __syncthreads();
     if (bad) {
-        for (int i = tid; i < n; i += NTHR) co[i] = __builtin_nan("");
+        for (int i = tid; i < n; i += NT) co[i] = __builtin_nan("");
         if (tid == 0) a.status[sol] = ARGUS_ESINGULAR;
         return;
     }
-    for (int idx = tid; idx < ntri; idx += NTHR) {
-        int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-        while ((r + 1) * (r + 2) / 2 <= idx) ++r;
-        while (r * (r + 1) / 2 > idx) --r;
-        int c = idx - r * (r + 1) / 2;
-        L[idx] *= dd[r] * dd[c];
+    // Jacobi scaling
+    for (int r = wv; r < n; r += NWV) {
+        const double dr = dd[r];
+        for (int c = lane; c <= r; c += 64) L[roff[r] + c] *= dr * dd[c];
     }
-    for (int r = tid; r < n; r += NTHR) bb[r] *= dd[r];
+    for (int r = tid; r < n; r += NT) bb[r] *= dd[r];
     __syncthreads();
     double mx = 0.0;
-    for (int r = tid; r < n; r += NTHR) mx = fmax(mx, L[r * (r + 1) / 2 + r]);
+    for (int r = tid; r < n; r += NT) mx = fmax(mx, L[roff[r] + r]);
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    if (lane == 0) red[wv] = mx;
     __syncthreads();
     double maxdiag = 0.0;
-    for (int i = 0; i < NTHR / 64; ++i) maxdiag = fmax(maxdiag, red[i]);
+    for (int i = 0; i < NWV; ++i) maxdiag = fmax(maxdiag, red[i]);
     const double tol = (double)n * 0x1p-52 * maxdiag;
     __syncthreads();
-    // right-looking Cholesky
-    for (int j = 0; j < n; ++j) {
-        double piv = L[j * (j + 1) / 2 + j];
+    // right-looking Cholesky, one barrier per column
+    for (int j = 0; j <= n; ++j) {
+        if (j > 0) {
+            // column j-1: L_i,j-1 = a_i,j-1 / sqrt(a_j-1,j-1) for i > j-1; the
+            // diagonal stays a_j-1,j-1 (every thread reads it here), the
+            // substitutions use rdiag = 1 / L_j-1,j-1
+            const double pv = L[roff[j - 1] + j - 1];
+            const double rs = 1.0 / sqrt(pv);
+            for (int i = j + tid; i < n; i += NT) L[roff[i] + j - 1] *= rs;
+            if (tid == 0) rdiag[j - 1] = rs;
+        }
+        if (j == n) break;
+        const double piv = L[roff[j] + j];
         if (!(piv > tol)) {
             if (tid == 0) bad = 1;
             break;
         }
-        double ljj = sqrt(piv);
-        __syncthreads();
-        for (int i = j + 1 + tid; i < n; i += NTHR) L[i * (i + 1) / 2 + j] /= ljj;
-        if (tid == 0) L[j * (j + 1) / 2 + j] = ljj;
-        __syncthreads();
-        // trailing update of rows i > j, columns j < c <= i (16 x 16 thread grid)
-        for (int i = j + 1 + (tid & 15); i < n; i += 16) {
-            const double lij = L[i * (i + 1) / 2 + j];
-            double *Li = L + i * (i + 1) / 2;
-            for (int c = j + 1 + (tid >> 4); c <= i; c += 16) Li[c] -= lij * L[c * (c + 1) / 2 + j];
+        const double ip = 1.0 / piv;
+        // trailing update of rows i > j, columns j < c <= i with the unscaled
+        // column j: a wave per row, its lanes on consecutive columns
+        for (int i = j + 1 + wv; i < n; i += NWV) {
+            const double lij = L[roff[i] + j] * ip;
+            double *Li = L + roff[i];
+            for (int c = j + 1 + lane; c <= i; c += 64) Li[c] -= lij * L[roff[c] + j];
         }
         __syncthreads();
     }
     __syncthreads();
     if (bad) {
-        for (int i = tid; i < n; i += NTHR) co[i] = __builtin_nan("");
+        for (int i = tid; i < n; i += NT) co[i] = __builtin_nan("");
         if (tid == 0) a.status[sol] = ARGUS_ESINGULAR;
         return;
     }
@@ -263,18 +282,18 @@ __global__ __launch_bounds__(NTHR) void fit_solve_kernel(SolveArgs a) {
     if (tid < 64) {
         for (int i = 0; i < n; ++i) {
             double s = 0.0;
-            for (int k = tid; k < i; k += 64) s += L[i * (i + 1) / 2 + k] * bb[k];
+            for (int k = tid; k < i; k += 64) s += L[roff[i] + k] * bb[k];
             for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            double v = (bb[i] - s) / L[i * (i + 1) / 2 + i];
+            double v = (bb[i] - s) * rdiag[i];
             __builtin_amdgcn_wave_barrier();
             bb[i] = v;      // every lane stores the same value, so each lane sees it
             __builtin_amdgcn_wave_barrier();
         }
         for (int i = n - 1; i >= 0; --i) {
             double s = 0.0;
-            for (int k = i + 1 + tid; k < n; k += 64) s += L[k * (k + 1) / 2 + i] * bb[k];
+            for (int k = i + 1 + tid; k < n; k += 64) s += L[roff[k] + i] * bb[k];
             for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            double v = (bb[i] - s) / L[i * (i + 1) / 2 + i];
+            double v = (bb[i] - s) * rdiag[i];
             __builtin_amdgcn_wave_barrier();
             bb[i] = v;
             __builtin_amdgcn_wave_barrier();
@@ -468,7 +487,7 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
     sa.n_fit = n_fit;
     sa.status = status;
     sa.gtri = nullptr;
-    size_t lds = ((size_t)sa.n * (sa.n + 1) / 2 + 2 * sa.n + 8) * sizeof(double);
+    size_t lds = ((size_t)sa.n * (sa.n + 1) / 2 + 2 * sa.n + SOLVE_THREADS / 64) * sizeof(double);
     int dev_max = 0;
     ARGUS_HIP_CHECK(ctx, hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                                ctx->device));
@@ -479,12 +498,12 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
         if (used + tri > ctx->ws_bytes)
             return argus_fail(ctx, ARGUS_ENOMEM, "solve storage does not fit the workspace");
         sa.gtri = sums + (size_t)n_regions * fa.stride;
-        lds = ((size_t)2 * sa.n + 8) * sizeof(double);
+        lds = ((size_t)2 * sa.n + SOLVE_THREADS / 64) * sizeof(double);
     }
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)fit_solve_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     argus_time_begin(ctx);
-    hipLaunchKernelGGL(fit_solve_kernel, dim3(n_regions), dim3(NTHR), lds, ctx->stream, sa);
+    hipLaunchKernelGGL(fit_solve_kernel, dim3(n_regions), dim3(SOLVE_THREADS), lds, ctx->stream, sa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     argus_time_end(ctx, "fit_solve");
     return ARGUS_OK;

@@ -227,6 +227,78 @@ __global__ __launch_bounds__(256) void coadd_kernel(CoaddArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Calibration of N raw frames that share one set of masters, fused with their
+// clipped-mean coadd: per pixel the N calibrated values, variances and masks
+// stay in registers, so only the raw frames and the masters are read and only
+// the coadd is written (about 29 instead of 155 bytes per pixel for N = 5).
+// The arithmetic is that of calibrate_kernel followed by coadd_kernel.
+struct CalCoaddArgs {
+    const uint16_t *raw[ARGUS_MAX_FRAMES];
+    CalArgs cal;               // masters, gain terms, saturation (cal/var/mask outputs unused)
+    CoaddArgs co;              // kappa, iterations and the coadd outputs (inputs unused)
+};
+
+template <int N>
+__global__ __launch_bounds__(256) void calcoadd_kernel(CalCoaddArgs a) {
+    const CoaddArgs &c = a.co;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)c.H * c.chunks;
+    if (t >= total) return;
+    int y = (int)(t / c.chunks);
+    int x0 = (int)(t - (int64_t)y * c.chunks) * CO_PX;
+    int64_t o = (int64_t)y * c.pitch + x0;
+    int n = min(CO_PX, c.W - x0);
+    float x[CO_PX][N], v[CO_PX][N];
+    uint8_t m[CO_PX][N];
+    if (c.vec && n == CO_PX) {
+        const float4 d4 = *(const float4 *)(a.cal.dark + o), f4 = *(const float4 *)(a.cal.flat + o);
+        const uint32_t b4 = a.cal.bpm ? *(const uint32_t *)(a.cal.bpm + o) : 0u;
+        const float d[CO_PX] = {d4.x, d4.y, d4.z, d4.w}, f[CO_PX] = {f4.x, f4.y, f4.z, f4.w};
+        uint2 r4[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) r4[i] = *(const uint2 *)(a.raw[i] + o);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const uint16_t r[CO_PX] = {(uint16_t)(r4[i].x & 0xffff), (uint16_t)(r4[i].x >> 16),
+                                       (uint16_t)(r4[i].y & 0xffff), (uint16_t)(r4[i].y >> 16)};
+#pragma unroll
+            for (int p = 0; p < CO_PX; ++p)
+                cal_one(a.cal, r[p], d[p], f[p], (uint8_t)(b4 >> (8 * p)), x[p][i], v[p][i], m[p][i]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < CO_PX; ++p) {
+            const bool in = p < n;
+            const float d = in ? a.cal.dark[o + p] : 0.f, f = in ? a.cal.flat[o + p] : 1.f;
+            const uint8_t b = in && a.cal.bpm ? a.cal.bpm[o + p] : 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                cal_one(a.cal, in ? a.raw[i][o + p] : (uint16_t)0, d, f, b, x[p][i], v[p][i], m[p][i]);
+                if (!in) m[p][i] = ARGUS_BAD;
+            }
+        }
+    }
+    float r[CO_PX], rv[CO_PX];
+    uint8_t rm[CO_PX], nu[CO_PX];
+#pragma unroll
+    for (int p = 0; p < CO_PX; ++p) coadd_one<N>(c, x[p], v[p], m[p], r[p], rv[p], rm[p], nu[p]);
+    if (c.vec && n == CO_PX) {
+        *(float4 *)(c.ref + o) = make_float4(r[0], r[1], r[2], r[3]);
+        *(float4 *)(c.ref_var + o) = make_float4(rv[0], rv[1], rv[2], rv[3]);
+        *(uint32_t *)(c.ref_mask + o) = rm[0] | (rm[1] << 8) | (rm[2] << 16) | ((uint32_t)rm[3] << 24);
+        if (c.n_used)
+            *(uint32_t *)(c.n_used + o) = nu[0] | (nu[1] << 8) | (nu[2] << 16) | ((uint32_t)nu[3] << 24);
+    } else {
+        for (int p = 0; p < n; ++p) {
+            c.ref[o + p] = r[p];
+            c.ref_var[o + p] = rv[p];
+            c.ref_mask[o + p] = rm[p];
+            if (c.n_used) c.n_used[o + p] = nu[p];
+        }
+    }
+}
+
 inline bool aligned(const void *p, size_t al) { return ((uintptr_t)p % al) == 0; }
 
 }  // namespace
@@ -283,5 +355,42 @@ int launch_coadd(argus_ctx *ctx, argus_dims d, int n, const float *const *cal,
     }
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     argus_time_end(ctx, "coadd");
+    return ARGUS_OK;
+}
+
+int launch_calibrate_coadd(argus_ctx *ctx, argus_dims d, int n, const uint16_t *const *raw,
+                           const float *dark, const float *flat, const uint8_t *bpm, float gain,
+                           float rn, uint16_t sat, float kappa, int max_iter, float *ref,
+                           float *ref_var, uint8_t *ref_mask, uint8_t *n_used) {
+    CalCoaddArgs a = {};
+    a.cal.dark = dark; a.cal.flat = flat; a.cal.bpm = bpm;
+    a.cal.inv_g = 1.0 / (double)gain;
+    a.cal.rn2_g2 = (double)rn * (double)rn / ((double)gain * (double)gain);
+    a.cal.sat = (float)sat;
+    bool vec = (d.pitch % CO_PX == 0) && aligned(dark, 16) && aligned(flat, 16) &&
+               (!bpm || aligned(bpm, 4)) && aligned(ref, 16) && aligned(ref_var, 16) &&
+               aligned(ref_mask, 4) && (!n_used || aligned(n_used, 4));
+    for (int i = 0; i < ARGUS_MAX_FRAMES; ++i) {
+        a.raw[i] = i < n ? raw[i] : nullptr;
+        if (i < n) vec = vec && aligned(raw[i], 8);
+    }
+    CoaddArgs &c = a.co;
+    c.ref = ref; c.ref_var = ref_var; c.ref_mask = ref_mask; c.n_used = n_used;
+    c.pitch = d.pitch; c.W = d.width; c.H = d.height;
+    c.chunks = (d.width + CO_PX - 1) / CO_PX;
+    c.kappa2 = (double)kappa * (double)kappa;
+    c.max_iter = max_iter;
+    c.vec = vec;
+    int64_t total = (int64_t)c.H * c.chunks;
+    dim3 grid((unsigned)((total + 255) / 256));
+    argus_time_begin(ctx);
+    switch (n) {
+#define ARGUS_CC(N) case N: hipLaunchKernelGGL(calcoadd_kernel<N>, grid, dim3(256), 0, ctx->stream, a); break;
+        ARGUS_CC(1) ARGUS_CC(2) ARGUS_CC(3) ARGUS_CC(4) ARGUS_CC(5) ARGUS_CC(6) ARGUS_CC(7) ARGUS_CC(8)
+#undef ARGUS_CC
+        default: return argus_fail(ctx, ARGUS_EINVAL, "bad frame count");
+    }
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, "calibrate_coadd");
     return ARGUS_OK;
 }

@@ -64,8 +64,15 @@ class Pipeline:
         self.ctx.calibrate(raw, self.dark, self.flat, self.bpm, self.gain, self.read_noise,
                            self.sat_adu, cal, var, mask)
 
-    def build_reference(self, raws):
-        """Calibrate every raw reference frame and coadd them (or copy one)."""
+    def build_reference(self, raws, fused: bool = True):
+        """Calibrate the raw reference frames and coadd them: in one fused
+        call (default), or by calibrating each frame into scratch planes and
+        coadding those (bit-identical results)."""
+        if fused:
+            self.ctx.calibrate_coadd(raws, self.dark, self.flat, self.bpm, self.gain,
+                                     self.read_noise, self.sat_adu, self.kappa, self.max_iter,
+                                     self.ref, self.ref_var, self.ref_mask, self.n_used)
+            return
         t = self.torch
         while len(self._cal_scratch) < len(raws):
             self._cal_scratch.append((t.empty_like(self.ref), t.empty_like(self.ref_var),

@@ -104,6 +104,48 @@ def test_coadd_parity(ctx, n):
     assert ulp_diff(g_rv, rv).max() <= 4
 
 
+# Fused calibration + coadd: bit-identical to the two calls (odd width and a
+# padded pitch take the scalar path at row ends), and within the coadd bars
+# of the oracle's calibrate-then-coadd.
+@pytest.mark.parametrize("n,pad", [(5, 0), (3, 13), (8, 0)])
+def test_calibrate_coadd_fused(ctx, n, pad):
+    import torch
+    fp = synth.make_pair(203, 150, 150, 19, 2.0, 2.6, n_ref=n, realistic_masters=True,
+                         cosmic_rate=3e-3, n_transients=0)
+    raws = [r.copy() for r in fp.ref_raw]
+    raws[0][7, 9] = 65535                            # saturated in one frame
+    dark, flat, bpm = fp.dark.copy(), fp.flat.copy(), fp.bpm.copy()
+    flat[3, 4] = 0.0                                  # BAD in every frame: NODATA
+    H, W = raws[0].shape
+    t = lambda x: padded(dev(x), pad) if pad else dev(x)
+    draws = [t(r) for r in raws]
+    ddark, dflat, dbpm = t(dark), t(flat), t(bpm)
+    mk = lambda: [padded(empty((H, W), d), pad) if pad else empty((H, W), d)
+                  for d in (torch.float32, torch.float32, torch.uint8, torch.uint8)]
+    fused = mk()
+    ctx.calibrate_coadd(draws, ddark, dflat, dbpm, 1.3, 1.7, 65535, 3.0, 5, *fused)
+    scratch = [mk()[:3] for _ in range(n)]
+    for r, (c, v, m) in zip(draws, scratch):
+        ctx.calibrate(r, ddark, dflat, dbpm, 1.3, 1.7, 65535, c, v, m)
+    two = mk()
+    ctx.coadd([c for c, _, _ in scratch], [v for _, v, _ in scratch],
+              [m for _, _, m in scratch], 3.0, 5, *two)
+    f, g = [host(x) for x in fused], [host(x) for x in two]
+    for a_, b_ in zip(f, g):
+        assert np.array_equal(a_.view(np.uint8), b_.view(np.uint8))
+    cals, vars_, masks = [], [], []
+    for r in raws:
+        c, v, m = oracle.calibrate(r, dark, flat, bpm, 1.3, 1.7, 65535)
+        cals.append(c.astype(np.float32))
+        vars_.append(v.astype(np.float32))
+        masks.append(m)
+    ref, rv, rm, nu = oracle.coadd(cals, vars_, masks, 3.0, 5)
+    assert np.array_equal(f[3], nu) and np.array_equal(f[2], rm)
+    assert rm[3, 4] & oracle.NODATA and rm[7, 9] & oracle.SAT
+    assert ulp_diff(f[0], ref).max() <= 4
+    assert ulp_diff(f[1], rv).max() <= 4
+
+
 # ---------------------------------------------------------------------- subtract
 def _noisy_pair(W, H, seed, n_stars=120):
     fp = synth.make_pair(W, H, n_stars, seed, 2.0, 2.6, n_transients=4)
