@@ -398,7 +398,7 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
 }
 
 template <int HH, int TILE, int PREC>
-__global__ __launch_bounds__(NTHR) void batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(NTHR, 2) void batch_kernel(BatchArgs a) {
     extern __shared__ float lds[];
     __shared__ int s_item;
     for (;;) {
