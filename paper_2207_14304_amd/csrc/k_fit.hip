@@ -173,6 +173,9 @@ constexpr int SOLVE_THREADS = 1024;
 // factorisation takes one barrier per column: step j updates the trailing
 // matrix with the unscaled column j (a_ic -= a_ij a_cj / a_jj) and scales
 // column j - 1, which no thread reads during step j.
+// GLT: the factor lives in global memory (a.gtri, for devices whose LDS is too
+// small); otherwise it is in LDS and every access is a plain LDS instruction.
+template <bool GLT>
 __global__ __launch_bounds__(SOLVE_THREADS) void fit_solve_kernel(SolveArgs a) {
     constexpr int NT = SOLVE_THREADS, NWV = NT / 64;
     extern __shared__ double sl[];
@@ -183,8 +186,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void fit_solve_kernel(SolveArgs a) {
     const int n = a.n, tid = threadIdx.x, sol = blockIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int ntri = n * (n + 1) / 2;
-    double *L = a.gtri ? a.gtri + (size_t)sol * ntri : sl;
-    double *bb = sl + (a.gtri ? 0 : ntri);
+    double *L = GLT ? a.gtri + (size_t)sol * ntri : sl;
+    double *bb = sl + (GLT ? 0 : ntri);
     double *dd = bb + n;
     double *red = dd + n;                 // [NWV]
     __shared__ int bad;
@@ -500,10 +503,13 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
         sa.gtri = sums + (size_t)n_regions * fa.stride;
         lds = ((size_t)2 * sa.n + SOLVE_THREADS / 64) * sizeof(double);
     }
-    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)fit_solve_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const void *kfn = sa.gtri ? (const void *)fit_solve_kernel<true> : (const void *)fit_solve_kernel<false>;
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     argus_time_begin(ctx);
-    hipLaunchKernelGGL(fit_solve_kernel, dim3(n_regions), dim3(SOLVE_THREADS), lds, ctx->stream, sa);
+    if (sa.gtri)
+        hipLaunchKernelGGL(fit_solve_kernel<true>, dim3(n_regions), dim3(SOLVE_THREADS), lds, ctx->stream, sa);
+    else
+        hipLaunchKernelGGL(fit_solve_kernel<false>, dim3(n_regions), dim3(SOLVE_THREADS), lds, ctx->stream, sa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     argus_time_end(ctx, "fit_solve");
     return ARGUS_OK;
