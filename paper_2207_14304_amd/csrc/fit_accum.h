@@ -478,8 +478,10 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx_begin, int sx_end,
     const int Xc = in_x ? Xin : (Xin < 0 ? 0 : a.W - 1);
     auto fetch_in = [&](int yy) {
         if (tid < L::IN) {
-            pr = a.ref[(int64_t)yy * P + Xc];
-            pm = a.rmask[(int64_t)yy * P + Xc];
+            // (global loads: the batch builds these arguments from a frame
+            // table, where the compiler cannot see the address space)
+            pr = gld(a.ref + (int64_t)yy * P + Xc);
+            pm = gld(a.rmask + (int64_t)yy * P + Xc);
             pin = in_x;
         }
     };
@@ -490,10 +492,10 @@ __device__ void fit_wave(const FitArgs &a, float *lds, int sx_begin, int sx_end,
             pok = lane_ok && y >= ry0 && y < ry1;
             const int yc = y < ry1 ? y : ry1 - 1;
             const int64_t o = (int64_t)yc * P + xw;
-            p_s = a.sci[o];
-            p_sv = a.svar[o];
-            p_rv = a.rvar[o];
-            p_sm = a.smask[o];
+            p_s = gld(a.sci + o);
+            p_sv = gld(a.svar + o);
+            p_rv = gld(a.rvar + o);
+            p_sm = gld(a.smask + o);
         }
     };
     uint32_t hist = 0;                     // bit j: input row yy-j has a flagged pixel in reach

@@ -54,6 +54,19 @@ struct argus_ctx {
     int n_cu = 0;                      // compute units of the device
 };
 
+// Loads and stores through a device pointer that addresses global memory, for
+// pointers the compiler cannot trace to a kernel argument (loaded from a
+// table): the explicit address space gives global rather than flat
+// instructions (flat ones also count against the LDS wait counter).
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // ---- helpers implemented in argus.hip --------------------------------------
 int argus_fail(argus_ctx *ctx, int code, const char *fmt, ...);
 int argus_ws_reserve(argus_ctx *ctx, size_t bytes);

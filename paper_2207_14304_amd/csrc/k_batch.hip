@@ -168,6 +168,8 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
     constexpr int K = BL::K, TH = BL::TH, TW = BL::TW, MW = BL::MW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const argus_cutout cu = a.cuts[c];
+    // (the frame planes come from a table: loads through them use gld so that
+    // they are global, not flat, accesses)
     const argus_frame fr = a.frames[cu.frame];
     const int L = cu.side;
     const int64_t P = fr.pitch;
@@ -258,9 +260,9 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
                     X = X < 0 ? 0 : (X >= L ? L - 1 : X);
                     Y = Y < 0 ? 0 : (Y >= L ? L - 1 : Y);
                     const int64_t o = org + (int64_t)Y * P + X;
-                    hr[j] = fr.ref[o];
-                    hv[j] = fr.ref_var[o];
-                    hm[j] = fr.ref_mask[o];
+                    hr[j] = gld(fr.ref + o);
+                    hv[j] = gld(fr.ref_var + o);
+                    hm[j] = gld(fr.ref_mask + o);
                 }
 #pragma unroll
                 for (int j = 0; j < NB8; ++j) {
@@ -327,14 +329,14 @@ __device__ void process_cutout(const BatchArgs &a, int c, float *lds) {
                     if (X >= L) continue;
                     const int64_t o = org + (int64_t)Y * P + X;
                     const bool edge = X < HH || X > L - 1 - HH || Y < HH || Y > L - 1 - HH;
-                    const uint8_t dm = fr.sci_mask[o] | (edge ? ARGUS_EDGE : 0u) |
+                    const uint8_t dm = gld(fr.sci_mask + o) | (edge ? ARGUS_EDGE : 0u) |
                                        ((!edge && foot[i]) ? ARGUS_FOOT : 0u);
                     float dval = 0.f, vval = 0.f;
                     if (dm == 0) {
-                        const float sv = fr.sci_var[o];
-                        dval = fr.sci[o] - (float)((double)m[i] + (double)bg);
+                        const float sv = gld(fr.sci_var + o);
+                        dval = gld(fr.sci + o) - (float)((double)m[i] + (double)bg);
                         vval = sv + v[i];
-                        const float tot = sv + fr.ref_var[o];
+                        const float tot = sv + gld(fr.ref_var + o);
                         if (tot > 0.f) {
                             c2 += (double)dval * (double)dval / (double)tot;
                             cnt += 1.0;

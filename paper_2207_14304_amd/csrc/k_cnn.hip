@@ -490,7 +490,7 @@ struct StampArgs {
 
 // Border median of an n x n stamp (4(n-1) values) by a wave-wide bitonic
 // sort in a 256-slot LDS buffer; the middle pair is averaged in FP32.
-__device__ float border_median_wave(const float *st, int n, float *buf, int lane) {
+__device__ __forceinline__ float border_median_wave(const float *st, int n, float *buf, int lane) {
     const int nb = 4 * (n - 1);
     for (int i = lane; i < 256; i += 64) {
         float v = __builtin_inff();

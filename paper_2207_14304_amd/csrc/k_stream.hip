@@ -22,20 +22,35 @@ struct CalArgs {
     int vec;                  // all planes 16-byte aligned for vector access
 };
 
-// cal = (raw - dark)/flat, var = (max(raw - dark, 0)/g + rn^2/g^2)/flat^2.
-// raw - dark is exact in FP64 (raw is an integer below 2^16, dark a float);
-// the divisions are correctly rounded FP64, so each output is the FP64 value
-// rounded once to FP32.
-__device__ __forceinline__ void cal_one(const CalArgs &a, uint16_t r, float d, float f,
-                                        uint8_t b, float &c, float &v, uint8_t &m) {
-    bool bad = (b != 0) || !(f > 0.f) || !__builtin_isfinite(f) || !__builtin_isfinite(d);
-    double sig = (double)r - (double)d;
-    double fd = (double)f;
-    double cd = sig / fd;
-    double vd = (fmax(sig, 0.0) * a.inv_g + a.rn2_g2) / (fd * fd);
-    c = bad ? 0.f : (float)cd;
-    v = bad ? 0.f : (float)vd;
-    m = (bad ? ARGUS_BAD : 0u) | ((float)r >= a.sat ? ARGUS_SAT : 0u);
+// cal = (raw - dark)/flat, var = (max(raw - dark, 0)/g + rn^2/g^2)/flat^2,
+// evaluated in FP64 and rounded once to FP32.  raw - dark is exact in FP64
+// (raw is an integer below 2^16, dark a float); the division by the flat is a
+// multiplication by its FP64 reciprocal, computed once per pixel (and shared
+// by every frame of a fused calibration), which is within one FP64 ulp of the
+// quotient.
+struct CalPix {
+    double rf, rf2;            // 1 / flat, its square
+    double d;
+    bool bad;
+};
+
+__device__ __forceinline__ CalPix cal_pix(float d, float f, uint8_t b) {
+    CalPix p;
+    p.bad = (b != 0) || !(f > 0.f) || !__builtin_isfinite(f) || !__builtin_isfinite(d);
+    p.rf = 1.0 / (double)f;
+    p.rf2 = p.rf * p.rf;
+    p.d = (double)d;
+    return p;
+}
+
+__device__ __forceinline__ void cal_one(const CalArgs &a, uint16_t r, const CalPix &p, float &c,
+                                        float &v, uint8_t &m) {
+    double sig = (double)r - p.d;
+    double cd = sig * p.rf;
+    double vd = (fmax(sig, 0.0) * a.inv_g + a.rn2_g2) * p.rf2;
+    c = p.bad ? 0.f : (float)cd;
+    v = p.bad ? 0.f : (float)vd;
+    m = (p.bad ? ARGUS_BAD : 0u) | ((float)r >= a.sat ? ARGUS_SAT : 0u);
 }
 
 __global__ __launch_bounds__(256) void calibrate_kernel(CalArgs a) {
@@ -60,7 +75,7 @@ __global__ __launch_bounds__(256) void calibrate_kernel(CalArgs a) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             uint8_t b = (uint8_t)(((i < 4 ? b8.x : b8.y) >> (8 * (i & 3))) & 0xff);
-            cal_one(a, r[i], d[i], f[i], b, c[i], v[i], m[i]);
+            cal_one(a, r[i], cal_pix(d[i], f[i], b), c[i], v[i], m[i]);
         }
         *(float4 *)(a.cal + o) = make_float4(c[0], c[1], c[2], c[3]);
         *(float4 *)(a.cal + o + 4) = make_float4(c[4], c[5], c[6], c[7]);
@@ -78,7 +93,7 @@ __global__ __launch_bounds__(256) void calibrate_kernel(CalArgs a) {
     for (int i = 0; i < n; ++i) {
         float c, v;
         uint8_t m;
-        cal_one(a, a.raw[o + i], a.dark[o + i], a.flat[o + i], a.bpm ? a.bpm[o + i] : 0, c, v, m);
+        cal_one(a, a.raw[o + i], cal_pix(a.dark[o + i], a.flat[o + i], a.bpm ? a.bpm[o + i] : 0), c, v, m);
         a.cal[o + i] = c;
         if (a.var) a.var[o + i] = v;
         a.mask[o + i] = m;
@@ -258,13 +273,15 @@ __global__ __launch_bounds__(256) void calcoadd_kernel(CalCoaddArgs a) {
         uint2 r4[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r4[i] = *(const uint2 *)(a.raw[i] + o);
+        CalPix cp[CO_PX];
+#pragma unroll
+        for (int p = 0; p < CO_PX; ++p) cp[p] = cal_pix(d[p], f[p], (uint8_t)(b4 >> (8 * p)));
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const uint16_t r[CO_PX] = {(uint16_t)(r4[i].x & 0xffff), (uint16_t)(r4[i].x >> 16),
                                        (uint16_t)(r4[i].y & 0xffff), (uint16_t)(r4[i].y >> 16)};
 #pragma unroll
-            for (int p = 0; p < CO_PX; ++p)
-                cal_one(a.cal, r[p], d[p], f[p], (uint8_t)(b4 >> (8 * p)), x[p][i], v[p][i], m[p][i]);
+            for (int p = 0; p < CO_PX; ++p) cal_one(a.cal, r[p], cp[p], x[p][i], v[p][i], m[p][i]);
         }
     } else {
 #pragma unroll
@@ -272,9 +289,10 @@ __global__ __launch_bounds__(256) void calcoadd_kernel(CalCoaddArgs a) {
             const bool in = p < n;
             const float d = in ? a.cal.dark[o + p] : 0.f, f = in ? a.cal.flat[o + p] : 1.f;
             const uint8_t b = in && a.cal.bpm ? a.cal.bpm[o + p] : 0;
+            const CalPix cp = cal_pix(d, f, b);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                cal_one(a.cal, in ? a.raw[i][o + p] : (uint16_t)0, d, f, b, x[p][i], v[p][i], m[p][i]);
+                cal_one(a.cal, in ? a.raw[i][o + p] : (uint16_t)0, cp, x[p][i], v[p][i], m[p][i]);
                 if (!in) m[p][i] = ARGUS_BAD;
             }
         }

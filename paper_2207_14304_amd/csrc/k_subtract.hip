@@ -43,11 +43,12 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
     using L = SubLds<HH>;
     constexpr int K = L::K, TH = L::TH, TW = L::TW, MW = L::MW, NP = (D + 1) * (D + 2) / 2;
     constexpr int NS = (D == 0) ? 2 : NP;               // constant kernel also keeps K^2
+    constexpr int NSP = NS <= 4 ? 4 : 8;                // per-tap values, padded to 16-byte reads
     extern __shared__ float lds[];
     float *Rt = lds;                                    // [TH][TW]
     float *Vt = Rt + TH * TW;                           // [TH][TW]
-    float *St = Vt + TH * TW;                           // [NS][K*K]
-    uint8_t *Mt = (uint8_t *)(St + NS * K * K);         // [TH][MW] ref mask != 0
+    float *St = Vt + TH * TW;                           // [K*K][NSP] stamp values per tap
+    uint8_t *Mt = (uint8_t *)(St + NSP * K * K);        // [TH][MW] ref mask != 0
     uint8_t *Mr = Mt + TH * MW;                         // [TH][BW] row-OR over 2h+1
     __shared__ double red[4][NTHR / 64];
 
@@ -114,8 +115,9 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
             for (int j = 0; j < NS_; ++j) {
                 const int i = tid + j * NTHR;
                 if (i < NP * K * K) {
-                    St[i] = sv_[j];
-                    if (D == 0 && i < K * K) St[K * K + i] = sv_[j] * sv_[j];
+                    const int t = i % (K * K), m = i / (K * K);
+                    St[t * NSP + m] = sv_[j];
+                    if (D == 0) St[t * NSP + 1] = sv_[j] * sv_[j];
                 }
             }
         }
@@ -148,24 +150,41 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
         for (int i = 0; i < PXT; ++i) { m[i] = 0.f; v[i] = 0.f; }
         if (Y < by1) {
             for (int vv = 0; vv < K; ++vv) {
-                const float *rr = Rt + (ly + 2 * HH - vv) * TW + lx0;
-                const float *qq = Vt + (ly + 2 * HH - vv) * TW + lx0;
-                float r[PXT + 2 * HH], q[PXT + 2 * HH];
+                // the windows of this kernel row as 16-byte reads (rows are
+                // 16-byte aligned; the last read may pass the window by two
+                // floats, inside the row)
+                constexpr int NW4 = (PXT + 2 * HH + 3) / 4;
+                const float4 *rr = (const float4 *)(Rt + (ly + 2 * HH - vv) * TW + lx0);
+                const float4 *qq = (const float4 *)(Vt + (ly + 2 * HH - vv) * TW + lx0);
+                float r[4 * NW4], q[4 * NW4];
 #pragma unroll
-                for (int j = 0; j < PXT + 2 * HH; ++j) { r[j] = rr[j]; q[j] = qq[j]; }
-                const float *st = St + vv * K;
+                for (int j = 0; j < NW4; ++j) {
+                    const float4 a4 = rr[j], b4 = qq[j];
+                    r[4 * j] = a4.x; r[4 * j + 1] = a4.y; r[4 * j + 2] = a4.z; r[4 * j + 3] = a4.w;
+                    q[4 * j] = b4.x; q[4 * j + 1] = b4.y; q[4 * j + 2] = b4.z; q[4 * j + 3] = b4.w;
+                }
 #pragma unroll
                 for (int uu = 0; uu < K; ++uu) {
+                    // this tap's stamp values, one or two 16-byte reads
+                    float st[NSP];
+                    {
+                        const float4 *sp = (const float4 *)(St + (vv * K + uu) * NSP);
+#pragma unroll
+                        for (int e = 0; e < NSP / 4; ++e) {
+                            const float4 v4 = sp[e];
+                            st[4 * e] = v4.x; st[4 * e + 1] = v4.y; st[4 * e + 2] = v4.z; st[4 * e + 3] = v4.w;
+                        }
+                    }
                     if constexpr (D == 0) {
-                        const float k = st[uu], k2 = st[K * K + uu];
+                        const float k = st[0], k2 = st[1];
 #pragma unroll
                         for (int i = 0; i < PXT; ++i) {
                             m[i] += k * r[i + 2 * HH - uu];
                             v[i] += k2 * q[i + 2 * HH - uu];
                         }
                     } else if constexpr (D == 1) {
-                        const float A0 = st[uu] + yt * st[K * K + uu];
-                        const float A1 = st[2 * K * K + uu];
+                        const float A0 = st[0] + yt * st[1];
+                        const float A1 = st[2];
 #pragma unroll
                         for (int i = 0; i < PXT; ++i) {
                             const float k = A0 + xt[i] * A1;
@@ -173,9 +192,9 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
                             v[i] += (k * k) * q[i + 2 * HH - uu];
                         }
                     } else {
-                        const float A0 = st[uu] + yt * (st[K * K + uu] + yt * st[2 * K * K + uu]);
-                        const float A1 = st[3 * K * K + uu] + yt * st[4 * K * K + uu];
-                        const float A2 = st[5 * K * K + uu];
+                        const float A0 = st[0] + yt * (st[1] + yt * st[2]);
+                        const float A1 = st[3] + yt * st[4];
+                        const float A2 = st[5];
 #pragma unroll
                         for (int i = 0; i < PXT; ++i) {
                             const float k = A0 + xt[i] * (A1 + xt[i] * A2);
@@ -313,7 +332,8 @@ int sub_launch(argus_ctx *ctx, SubArgs &a, int n_blocks) {
     using L = SubLds<HH>;
     constexpr int NP = (D + 1) * (D + 2) / 2;
     constexpr int NS = (D == 0) ? 2 : NP;
-    size_t lds = (size_t)2 * L::TH * L::TW * 4 + (size_t)NS * L::K * L::K * 4 +
+    constexpr int NSP = NS <= 4 ? 4 : 8;
+    size_t lds = (size_t)2 * L::TH * L::TW * 4 + (size_t)NSP * L::K * L::K * 4 +
                  (size_t)L::TH * L::MW + (size_t)L::TH * BW;
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)subtract_kernel<D, HH>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
