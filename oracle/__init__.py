@@ -29,4 +29,4 @@ from .core import (BAD, SAT, EDGE, NODATA, FOOT, DET, CAND,  # noqa: F401
                    KernelSpec, calibrate, coadd, basis, basis_meta, convolve,
                    monomials, norm_coords, tile_bounds, fit_set, design_rows,
                    normal_equations, cholesky, solve, fit_kernel, chi2,
-                   expand_kernel, subtract, detect, n_unknowns)
+                   expand_kernel, subtract, subtract_at, detect, n_unknowns)

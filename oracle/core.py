@@ -479,6 +479,53 @@ def subtract(stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec):
     return Dimg, Vimg, dmask, c2, nf
 
 
+def subtract_at(stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, ys, xs):
+    """The definitions of `subtract` evaluated at the pixels (ys, xs) only, in
+    the frame's own coordinates, for frames too large to difference whole.
+    Returns (D, V, diff_mask) at those pixels."""
+    stamps = np.asarray(stamps, np.float64)
+    bg = np.atleast_2d(np.asarray(bg, np.float64))
+    if stamps.ndim == 3:
+        stamps = stamps[None]
+    ys = np.asarray(ys, np.int64)
+    xs = np.asarray(xs, np.int64)
+    H, W = np.shape(ref)
+    h = spec.half_width
+    mons = monomials(spec.spatial_degree)
+    monb = monomials(spec.bg_degree)
+    xt, yt = norm_coords(W, H)
+    rm = np.asarray(ref_mask)
+    ref = np.asarray(ref)
+    ref_var = np.asarray(ref_var)
+    dmask = np.asarray(sci_mask, np.uint8)[ys, xs].copy()
+    edge = (xs < h) | (xs > W - 1 - h) | (ys < h) | (ys > H - 1 - h)
+    dmask |= np.where(edge, EDGE, 0).astype(np.uint8)
+    owner = np.zeros(ys.size, np.int64)
+    if spec.mode == PER_TILE:
+        for t, (x0, x1, y0, y1) in enumerate(_solve_regions(spec, W, H)):
+            owner[(xs >= x0) & (xs < x1) & (ys >= y0) & (ys < y1)] = t
+    D = np.zeros(ys.size)
+    V = np.zeros(ys.size)
+    off = np.arange(-h, h + 1)
+    for i in np.flatnonzero(~edge):
+        y, x = ys[i], xs[i]
+        # win[a][b] = image(x + b - h, y + a - h), which K(u, v) meets at u = h - b, v = h - a
+        if (rm[y - h:y + h + 1, x - h:x + h + 1] != 0).any():
+            dmask[i] |= FOOT
+        if dmask[i] != 0:
+            continue
+        s = owner[i]
+        P = np.array([xt[x] ** p * yt[y] ** q for (p, q) in mons])
+        Pb = np.array([xt[x] ** p * yt[y] ** q for (p, q) in monb])
+        Kp = np.tensordot(P, stamps[s], axes=1)       # K_p[v+h][u+h]
+        Kf = Kp[::-1, ::-1]
+        wr = ref[np.ix_(y + off, x + off)].astype(np.float64)
+        wv = ref_var[np.ix_(y + off, x + off)].astype(np.float64)
+        D[i] = float(sci[y, x]) - ((wr * Kf).sum() + Pb @ bg[s])
+        V[i] = float(sci_var[y, x]) + (wv * Kf * Kf).sum()
+    return D, V, dmask
+
+
 # ---------------------------------------------------------------------------
 # Detection: noise-normalised difference, threshold, local maxima, PSF flux.
 # ---------------------------------------------------------------------------

@@ -1,0 +1,234 @@
+"""GPU parity at the full IMX455 frame size (9576 x 6388 px), in the launch
+configuration the benchmark times: the fused 5-frame calibration + coadd, the
+science calibration, the global fit (D = 2, h = 10, 31 bases, FP32 moments,
+16 x 16 tiles ordering the partial sums), the subtraction and the detection.
+The oracle cannot difference a whole 61 MP frame in seconds, so each stage is
+checked on what it can compute at this size:
+
+* calibration and coadd: 65 536 sampled pixels plus the frame's corners, last
+  row and last column, computed by the oracle pixel by pixel from the same raw
+  values; masks and counts bit-exact, values within 2 (calibration) and 4
+  (coadd) FP32 ulp, the stage tests' bars;
+* fit: exact recovery, which holds at any size: a noise-free science frame
+  built from the reference and known coefficients must return them (stamps
+  within 3e-3 of the largest tap, the FP32 bar of the small-frame test; kernel
+  sum, the photometric ratio, within 1e-5);
+* subtraction: with known stamps, D, V and the mask at sampled pixels against
+  the oracle's per-pixel evaluation (RMS of the error <= 1e-4 sigma, max <=
+  1e-2 sigma, V within 1e-5), and chi^2 / n_fit against their definition
+  summed over the whole frame;
+* detection: the whole frame against the oracle (its vectorised form is fast
+  enough here), with the stage test's bars.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_14304_amd import argus, synth
+from gpu_util import dev, host, empty, ulp_diff
+from test_oracle_pins import _star_ref
+
+pytestmark = pytest.mark.gpu
+
+W, H = 9576, 6388
+SPEC_KW = dict(sigmas=(0.7, 1.5, 3.0), degrees=(4, 3, 2), half_width=10, spatial_degree=2,
+               bg_degree=2, tiles_x=16, tiles_y=16)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = argus.Context(0)
+    yield c
+    c.close()
+
+
+def _ospec(s):
+    return oracle.KernelSpec(sigmas=tuple(s.sigma[:s.n_gauss]), degrees=tuple(s.degree[:s.n_gauss]),
+                             half_width=s.half_width, spatial_degree=s.spatial_degree,
+                             bg_degree=s.bg_degree, tiles_x=s.tiles_x, tiles_y=s.tiles_y,
+                             mode=s.mode)
+
+
+def _samples(seed, n):
+    """n uniform pixels, the four corners, 64 on the last row, 64 on the last column."""
+    rng = np.random.default_rng(seed)
+    ys = np.r_[rng.integers(0, H, n), [0, 0, H - 1, H - 1], np.full(64, H - 1), rng.integers(0, H, 64)]
+    xs = np.r_[rng.integers(0, W, n), [0, W - 1, 0, W - 1], rng.integers(0, W, 64), np.full(64, W - 1)]
+    return ys, xs
+
+
+def test_full_frame_calibration_and_coadd_sampled(ctx):
+    import torch
+    from paper_2207_14304_amd.pipeline import Pipeline
+    fp = synth.make_pair(W, H, 60000, 2, None, None, True, 5, True, 800.0, 1.05, 20,
+                         cosmic_rate=1e-5)
+    spec = argus.make_spec(**SPEC_KW)
+    pipe = Pipeline(ctx, W, H, spec, synth.psf_image(7, 2.6))
+    pipe.set_masters(fp.dark, fp.flat, fp.bpm)
+
+    def up(a):
+        return torch.from_numpy(a.view(np.int16)).cuda().view(torch.uint16)
+
+    pipe.build_reference([up(r) for r in fp.ref_raw])
+    pipe.calibrate(up(fp.sci_raw), pipe.sci, pipe.sci_var, pipe.sci_mask)
+    ys, xs = _samples(7, 65536)
+    at = lambda t: host(t)[ys, xs]
+    g_ref, g_rv, g_rm, g_nu = at(pipe.ref), at(pipe.ref_var), at(pipe.ref_mask), at(pipe.n_used)
+    g_s, g_sv, g_sm = at(pipe.sci), at(pipe.sci_var), at(pipe.sci_mask)
+    dark, flat, bpm = fp.dark[ys, xs], fp.flat[ys, xs], fp.bpm[ys, xs]
+    cal = lambda raw: oracle.calibrate(raw[ys, xs], dark, flat, bpm, 1.0, 1.7, 65535)
+    c, v, m = cal(fp.sci_raw)
+    assert np.array_equal(g_sm, m)
+    assert ulp_diff(g_s, c).max() <= 2 and ulp_diff(g_sv, v).max() <= 2
+    cals, vars_, masks = [], [], []
+    for r in fp.ref_raw:
+        c, v, m = cal(r)
+        cals.append(c.astype(np.float32))
+        vars_.append(v.astype(np.float32))
+        masks.append(m)
+    ref, rv, rm, nu = oracle.coadd(cals, vars_, masks, 3.0, 5)
+    assert np.array_equal(g_nu, nu) and np.array_equal(g_rm, rm)
+    assert ulp_diff(g_ref, ref).max() <= 4 and ulp_diff(g_rv, rv).max() <= 4
+    print(f"full-frame calibration/coadd: {ys.size} samples, {int((nu < 5).sum())} with clipped frames")
+
+
+def _in_span_science(ref32, spec_o, a):
+    """S = sum_m P_m (R (x) K_m) + sum_m bg_m P_m for one global solve, the
+    convolutions by FFT (exact up to rounding away from the border, where the
+    fit does not look)."""
+    from scipy import fft
+    st, bgc = oracle.expand_kernel(a, spec_o)
+    K = st.shape[-1]
+    h = K // 2
+    fshape = [fft.next_fast_len(n, real=True) for n in (H + K - 1, W + K - 1)]
+    FR = fft.rfft2(ref32.astype(np.float64), fshape, workers=-1)
+    xt, yt = oracle.norm_coords(W, H)
+    S = np.zeros((H, W))
+    for m, (p, q) in enumerate(oracle.monomials(spec_o.spatial_degree)):
+        full = fft.irfft2(FR * fft.rfft2(st[0, m], fshape, workers=-1), fshape, workers=-1)
+        S += (yt[:, None] ** q) * (xt[None, :] ** p) * full[h:h + H, h:h + W]
+    for m, (p, q) in enumerate(oracle.monomials(spec_o.bg_degree)):
+        S += bgc[0, m] * (yt[:, None] ** q) * (xt[None, :] ** p)
+    return S
+
+
+def test_full_frame_fit_recovery_and_subtraction(ctx):
+    import torch
+    from scipy import ndimage
+    spec = argus.make_spec(**SPEC_KW)
+    so = _ospec(spec)
+    n, ns = argus.kernel_dims(spec)
+    assert ns == 1 and n == 192
+    ref32 = _star_ref(W, H, 60000, 91, fwhm=2.0, sky=800.0).astype(np.float32)
+    rng = np.random.default_rng(92)
+    a = rng.uniform(-0.05, 0.05, n)
+    a[0] = 1.05
+    a[31 * 6] = -20.0
+    S = _in_span_science(ref32, so, a)
+    ones = torch.ones((H, W), dtype=torch.float32, device="cuda")
+    zeros = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    d_ref = dev(ref32)
+    # --- the fit on noise-free in-span data returns the generating kernel
+    co = empty((1, n), torch.float64)
+    nf = empty(1, torch.int64)
+    stt = empty(1, torch.int32)
+    ctx.fit_kernel(spec, d_ref, ones, zeros, dev(S.astype(np.float32)), ones, zeros, co, nf, stt)
+    K = 2 * spec.half_width + 1
+    g_st = empty((1, 6, K, K), torch.float32)
+    g_bg = empty((1, 6), torch.float32)
+    ctx.expand_kernel(spec, co, g_st, g_bg)
+    o_st, o_bg = oracle.expand_kernel(a, so)
+    assert int(host(stt)[0]) == 0
+    assert int(host(nf)[0]) == (W - 2 * spec.half_width) * (H - 2 * spec.half_width)
+    err = np.abs(host(g_st) - o_st).max() / np.abs(o_st).max()
+    print(f"full-frame exact recovery: stamp error {err:.2e}")
+    assert err <= 3e-3
+    assert np.allclose(host(g_bg), o_bg, rtol=1e-3, atol=0.05)
+    assert abs(host(co)[0, 0] - a[0]) <= 1e-5 * a[0]
+    del ones, zeros
+    # --- subtraction with known stamps on noisy, masked data
+    rv = (ref32.astype(np.float64) + 1.7 ** 2).astype(np.float32)
+    sv = (np.maximum(S, 0.0) + 1.7 ** 2).astype(np.float32)
+    sci = (S + np.sqrt(sv) * rng.standard_normal((H, W))).astype(np.float32)
+    del S
+    rm = np.zeros((H, W), np.uint8)
+    sat = rng.random((H, W)) < 2e-5
+    rm[sat] = oracle.SAT
+    sm = np.where(rng.random((H, W)) < 1e-4, oracle.BAD, 0).astype(np.uint8)
+    st32 = o_st.astype(np.float32)
+    bg32 = o_bg.astype(np.float32)
+    gD, gV, gM = (empty((H, W), t) for t in (torch.float32, torch.float32, torch.uint8))
+    c2 = empty(1, torch.float64)
+    nc = empty(1, torch.int64)
+    ctx.subtract(spec, dev(st32), dev(bg32), d_ref, dev(rv), dev(rm), dev(sci), dev(sv), dev(sm),
+                 gD, gV, gM, c2, nc)
+    gD, gV, gM = host(gD), host(gV), host(gM)
+    ys, xs = _samples(93, 65536)
+    sy, sx = np.nonzero(sat)                                    # and beside flagged pixels
+    pick = rng.choice(sy.size, 256, replace=False)
+    ys = np.r_[ys, np.clip(sy[pick] + rng.integers(-12, 13, 256), 0, H - 1)]
+    xs = np.r_[xs, np.clip(sx[pick] + rng.integers(-12, 13, 256), 0, W - 1)]
+    oD, oV, oM = oracle.subtract_at(st32.astype(np.float64), bg32.astype(np.float64), ref32, rv, rm,
+                                    sci, sv, sm, so, ys, xs)
+    assert np.array_equal(gM[ys, xs], oM)
+    ok = oM == 0
+    assert (oM & oracle.FOOT).any() and ok.sum() > 60000
+    e = (gD[ys, xs][ok] - oD[ok]) / np.sqrt(oV[ok])
+    rms, mx = np.sqrt(np.mean(e ** 2)), np.abs(e).max()
+    print(f"full-frame subtraction: {ys.size} samples, RMS {rms:.2e} max {mx:.2e} sigma")
+    assert rms <= 1e-4 and mx <= 1e-2
+    assert np.abs(gV[ys, xs][ok] / oV[ok] - 1).max() <= 1e-5
+    assert np.all(gD[ys, xs][~ok] == 0) and np.all(gV[ys, xs][~ok] == 0)
+    # chi^2 and its count over the whole fit set: interior, clean footprint,
+    # unflagged science pixel, positive total variance
+    h = spec.half_width
+    dirty = ndimage.maximum_filter((rm != 0).astype(np.uint8), size=2 * h + 1, mode="constant")
+    phi = np.zeros((H, W), bool)
+    phi[h:H - h, h:W - h] = True
+    phi &= (dirty == 0) & (sm == 0) & (sv.astype(np.float64) + rv > 0)
+    w = 1.0 / (sv[phi].astype(np.float64) + rv[phi])
+    chi2_def = np.sum(w * gD[phi].astype(np.float64) ** 2)
+    assert int(host(nc)[0]) == int(phi.sum())
+    assert abs(host(c2)[0] / chi2_def - 1) <= 1e-6
+    print(f"full-frame chi2/n {chi2_def / phi.sum():.4f}")
+
+
+def test_full_frame_detection(ctx):
+    import torch
+    rng = np.random.default_rng(95)
+    V = (50 + 20 * rng.random((H, W))).astype(np.float32)
+    D = (rng.standard_normal((H, W)) * np.sqrt(V)).astype(np.float32)
+    P = synth.psf_image(7, 2.6)
+    r = 7
+    for _ in range(2000):
+        x, y = int(rng.integers(0, W)), int(rng.integers(0, H))
+        f = rng.uniform(200, 3000)
+        y0, y1, x0, x1 = max(y - r, 0), min(y + r + 1, H), max(x - r, 0), min(x + r + 1, W)
+        D[y0:y1, x0:x1] += (f * P[y0 - y + r:y1 - y + r, x0 - x + r:x1 - x + r]).astype(np.float32)
+    M = np.zeros((H, W), np.uint8)
+    M[rng.random((H, W)) < 0.01] = oracle.FOOT
+    M[:10] |= oracle.EDGE
+    M[-10:] |= oracle.EDGE
+    M[:, :10] |= oracle.EDGE
+    M[:, -10:] |= oracle.EDGE
+    cap = 65536
+    g_snr = empty((H, W), torch.float32)
+    g_det = empty((H, W), torch.uint8)
+    g_c = empty(cap * argus.CANDIDATE_DTYPE.itemsize, torch.uint8)
+    g_n = empty(1, torch.int32)
+    ctx.detect(dev(D), dev(V), dev(M), 5.0, dev(P, np.float32), r, g_snr, g_det, g_c, cap, g_n)
+    snr, det, cands = oracle.detect(D, V, M, 5.0, P)
+    gs, gd = host(g_snr), host(g_det)
+    n = int(host(g_n)[0])
+    gc = host(g_c)[: n * argus.CANDIDATE_DTYPE.itemsize].view(argus.CANDIDATE_DTYPE)
+    assert np.abs(gs - snr).max() <= 1e-4
+    near = np.abs(snr - 5.0) <= 1e-3
+    assert np.array_equal(gd[~near], det[~near])
+    print(f"full-frame detection: {n} candidates")
+    assert n == len(cands) and n > 1000
+    assert np.array_equal(gc["x"], cands["x"]) and np.array_equal(gc["y"], cands["y"])
+    assert np.allclose(gc["flux"], cands["flux"], rtol=1e-4)
+    assert np.allclose(gc["flux_err"], cands["flux_err"], rtol=1e-4)

@@ -424,6 +424,15 @@ def test_subtract_matches_brute_force_loops():
             assert V[y, x] == pytest.approx(sv[y, x] + vr, rel=1e-12)
             c2b[t] += (sci[y, x] - m) ** 2 / (sv[y, x] + rv[y, x])
     assert np.allclose(c2, c2b, rtol=1e-12)
+    # the per-pixel evaluator (used on frames too large to difference whole)
+    # gives the same values, in any pixel order
+    yy, xx = np.mgrid[0:H, 0:W]
+    order = rng.permutation(H * W)
+    Da, Va, dma = oracle.subtract_at(stamps, bg, ref, rv, rm, sci, sv, sm, spec,
+                                     yy.ravel()[order], xx.ravel()[order])
+    assert np.array_equal(dma, dm.ravel()[order])
+    assert np.allclose(Da, D.ravel()[order], rtol=1e-12, atol=1e-12)
+    assert np.allclose(Va, V.ravel()[order], rtol=1e-12, atol=1e-12)
 
 
 def test_delta_kernel_gives_zero_difference():
