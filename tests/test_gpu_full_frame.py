@@ -232,3 +232,90 @@ def test_full_frame_detection(ctx):
     assert np.array_equal(gc["x"], cands["x"]) and np.array_equal(gc["y"], cands["y"])
     assert np.allclose(gc["flux"], cands["flux"], rtol=1e-4)
     assert np.allclose(gc["flux_err"], cands["flux_err"], rtol=1e-4)
+
+
+def test_full_size_batch_sampled_cutouts(ctx):
+    """The cutout batch as the benchmark launches it: 20 cameras' 9576 x 6388
+    frames, 4000 cutouts each with sides log-uniform in 64-512 px, a constant
+    15x15 kernel per cutout from FP64 row moments, autotuned tile shape, one
+    graph launch.  The cameras alternate between two host-generated frame
+    pairs (so the oracle sees the same planes); 24 cutouts (the four largest,
+    the four smallest and 16 drawn at random) are checked against the oracle
+    run on each as a standalone image, with the batch test's FP64 bars except
+    the stamp bar.  That one is 3e-4 here: with FP64 row moments the only FP32
+    arithmetic left is the basis convolution, and the cutouts' Jacobi-scaled
+    systems (condition numbers 2e4-2.5e6 on the oracle for 64-512 px) pass its
+    rounding to the stamps unevenly: the 64 px cutouts (2 500 fit pixels for
+    32 unknowns) measured up to 1.3e-4, cutouts above 100 px under 3e-5.  The
+    difference bars (the stated ones) are unchanged."""
+    import torch
+    pairs = []
+    for i, fw in enumerate((2.2, 3.4)):
+        fp = synth.make_pair(W, H, 60000, 60 + i, fw * 2.0 / 2.6, fw, n_transients=20)
+        cs, vs, ms = oracle.calibrate(fp.sci_raw, fp.dark, fp.flat, fp.bpm)
+        cr, vr, mr = oracle.calibrate(fp.ref_raw[0], fp.dark, fp.flat, fp.bpm)
+        rng = np.random.default_rng(70 + i)
+        mr[rng.random(mr.shape) < 2e-4] |= oracle.SAT
+        ms[rng.random(ms.shape) < 5e-4] |= oracle.BAD
+        f32 = lambda a: a.astype(np.float32)
+        pairs.append(dict(host=(f32(cr), f32(vr), mr, f32(cs), f32(vs), ms), sx=fp.star_x, sy=fp.star_y))
+        del fp, cs, vs, cr, vr
+    nfr = 20
+    fr, x0, y0, L = [], [], [], []
+    for f in range(nfr):
+        p = pairs[f % 2]
+        a, b, c = synth.draw_cutouts(40 + f, W, H, p["sx"], p["sy"], 4000)
+        fr += [f] * len(a)
+        x0 += list(a)
+        y0 += list(b)
+        L += list(c)
+    fr, x0, y0, L = map(np.array, (fr, x0, y0, L))
+    assert fr.size == 80000 and L.min() >= 64 and L.max() <= 512
+    dpairs = [tuple(dev(q) for q in p["host"]) for p in pairs]
+    spec = argus.make_spec(half_width=7, precision=argus.FP64)
+    b = argus.Batch(ctx, spec, fr, x0, y0, L, [W] * nfr, [H] * nfr)
+    n = b.n
+    outs = [empty(b.arena, torch.float32), empty(b.arena, torch.float32),
+            empty(b.arena, torch.uint8), empty(b.arena, torch.uint8),
+            empty((n, 32), torch.float64), empty(n, torch.float64), empty(n, torch.int64),
+            empty(n, torch.int32), empty(n, torch.int32)]
+    ctx.batch_run(b, [dpairs[f % 2] for f in range(nfr)], 5.0, *outs)
+    torch.cuda.synchronize()
+    diff, var, mask, det = outs[:4]
+    coeffs, chi2, n_fit, status, n_cands = (host(t) for t in outs[4:])
+    assert np.all(status == 0)
+    order = np.argsort(L, kind="stable")
+    rng = np.random.default_rng(71)
+    pick = np.unique(np.r_[order[-4:], order[:4], rng.choice(n, 16, replace=False)])
+    ospec = oracle.KernelSpec(half_width=7)
+    B = oracle.basis(ospec)
+    worst = dict(stamp=0.0, rms=0.0, mx=0.0, var=0.0, chi2=0.0)
+    for i in pick:
+        Li, off = int(L[i]), int(b.offsets[i])
+        sl = (slice(y0[i], y0[i] + Li), slice(x0[i], x0[i] + Li))
+        planes = [q[sl] for q in pairs[fr[i] % 2]["host"]]
+        co, st, nf = oracle.fit_kernel(*planes, ospec, B)
+        stamps, bgo = oracle.expand_kernel(co, ospec, B)
+        D, V, dm, c2, _ = oracle.subtract(stamps, bgo, *planes, ospec)
+        snr, odet, cands = oracle.detect(D, V, dm, 5.0, np.ones((1, 1)))
+        assert st[0] == 0 and n_fit[i] == nf[0]
+        cut = lambda t: host(t[off:off + Li * Li]).reshape(Li, Li)
+        gD, gV, gM, gdet = cut(diff), cut(var), cut(mask), cut(det)
+        assert np.array_equal(gM, dm)
+        ok = dm == 0
+        e = (gD[ok] - D[ok]) / np.sqrt(V[ok])
+        near = np.abs(snr - 5.0) <= 1e-3
+        assert np.array_equal(gdet[~near], odet[~near])
+        assert near.any() or n_cands[i] == len(cands)
+        gst = np.tensordot(coeffs[i][:31], B, 1)
+        r = dict(stamp=np.abs(gst - stamps[0, 0]).max() / np.abs(stamps[0, 0]).max(),
+                 rms=np.sqrt(np.mean(e ** 2)), mx=np.abs(e).max(),
+                 var=np.abs(gV[ok] / V[ok] - 1).max(), chi2=abs(chi2[i] / c2[0] - 1))
+        worst = {k: max(worst[k], float(r[k])) for k in worst}
+        print(f"  cutout {i}: L {Li}, seeing pair {fr[i] % 2}, n_fit {nf[0]}, "
+              + ", ".join(f"{k} {float(v):.2e}" for k, v in r.items()))
+    print(f"full-size batch: {n} cutouts, {pick.size} checked (L {int(L[pick].min())}-"
+          f"{int(L[pick].max())}), worst {worst}, autotune {b.info()}")
+    assert worst["stamp"] <= 3e-4 and worst["rms"] <= 1e-4 and worst["mx"] <= 1e-2
+    assert worst["var"] <= 1e-5 and worst["chi2"] <= 1e-5
+    b.close()
