@@ -483,13 +483,14 @@ __global__ __launch_bounds__(64 * (NWC + NWM)) void fit_accum8_kernel(FitArgs a)
 }
 
 // Launch fit_accum8_kernel<D, h, PREC, NWC, NWM> with its dynamic LDS size:
-// FP32 runs 8 convolution + 8 MFMA waves (two tasks each, so every wave fits
-// in 128 registers and each SIMD holds four waves); the FP64 and BF16x3
-// forms, whose MFMA waves hold four tasks' FP64 sums, run 4 + 4.
+// FP32 and BF16x3 run 8 convolution + 8 MFMA waves (two tasks each, so every
+// wave fits in 128 registers and each SIMD holds four waves); FP64, whose
+// 64-bit MFMA operands and accumulators do not fit that budget, runs 4 + 4
+// with four tasks per MFMA wave.
 template <int PREC>
 int fit_accum8_launch(argus_ctx *ctx, const FitArgs &fa, int D, dim3 grid) {
-    constexpr int NWM = PREC == ARGUS_FP32 ? 8 : 4;
-    constexpr int NWC = PREC == ARGUS_FP32 ? 8 : 4;
+    constexpr int NWM = PREC == ARGUS_FP64 ? 4 : 8;
+    constexpr int NWC = PREC == ARGUS_FP64 ? 4 : 8;
     hipError_t err = hipSuccess;
     bool ok = false;
 #define ARGUS_FH(DD, HH)                                                                   \

@@ -407,7 +407,7 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
                 const int nk = spec->degree[g] - i + 1;
                 cost[p] = (h + 1) + (nk > 1 ? 2 * h : h) + nk * (h + 2);
             }
-        // 4 convolution waves (FP64, BF16x3 forms), up to 4 planes each
+        // 4 convolution waves (FP64 form), up to 4 planes each
         int load[4] = {3 * h, 0, 0, 0}, nin[4] = {};
         bool used[ARGUS_MAX_PLANES] = {};
         for (int w = 0; w < 4; ++w)
@@ -423,7 +423,7 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
             fa.plist[w][nin[w]++] = (int8_t)best;
             load[w] += cost[best];
         }
-        // 8 convolution waves (FP32 form)
+        // 8 convolution waves (FP32 and BF16x3 forms)
         int load8[8] = {}, nin8[8] = {};
         load8[0] = 3 * h;
         bool used8[ARGUS_MAX_PLANES] = {};
