@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--height", type=int, default=6388)
     p.add_argument("--stars", type=int, default=60000)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--two-cameras", type=int, default=1,
+                   help="also time two cameras' steps on two streams (0: skip)")
     p.add_argument("--cpu-crop", type=int, default=1024)
     p.add_argument("--batch-frames", type=int, default=20)
     p.add_argument("--batch-cutouts", type=int, default=4000)
@@ -459,12 +461,59 @@ def main():
     pipe.spec = spec
     log("precision variants: " + json.dumps(prec))
 
+    # two cameras sharing the GPU: a second pipeline with its own context on
+    # its own stream (both streams at the default priority), the two cameras'
+    # steps interleaved, so one camera's single-workgroup solve and the tails
+    # of its kernels overlap the other's work; aggregate throughput of both
+    two = None
+    if args.two_cameras:
+        ctx2 = argus.Context(0)
+        pipe2 = Pipeline(ctx2, W, H, spec, psf)
+        pipe2.set_masters(fp.dark, fp.flat, fp.bpm)
+        s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
+
+        def both(n):
+            for _ in range(n):
+                with torch.cuda.stream(s_a):
+                    step()
+                with torch.cuda.stream(s_b):
+                    pipe2.build_reference(refs)
+                    pipe2.difference(sci)
+
+        torch.cuda.synchronize()
+        both(2)
+        torch.cuda.synchronize()
+        cur = torch.cuda.current_stream()
+        t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea, eb = torch.cuda.Event(), torch.cuda.Event()
+        t0e.record(cur)
+        s_a.wait_event(t0e)
+        s_b.wait_event(t0e)
+        both(args.steps)
+        ea.record(s_a)
+        eb.record(s_b)
+        cur.wait_event(ea)
+        cur.wait_event(eb)
+        t1e.record(cur)
+        torch.cuda.synchronize()
+        ms2 = t0e.elapsed_time(t1e)
+        same = bool(torch.equal(pipe.diff, pipe2.diff) and torch.equal(pipe.coeffs, pipe2.coeffs))
+        two = {"value": round(2 * args.steps * npix / (ms2 / 1e3) / 1e6, 2), "unit": "Mpix/s",
+               "ms_per_frame": round(ms2 / (2 * args.steps), 4), "identical_to_one_camera": same,
+               "workload": "two cameras, each a full step (5-frame calibrate + coadd, "
+                           "difference), on two streams with interleaved steps"}
+        log("two cameras: " + json.dumps(two))
+        del pipe2
+        ctx2.close()
+
     del refs, sci, pipe
     torch.cuda.empty_cache()
     variants = {"precision": prec, "per_frame_difference": {
         "value": round(npix / (ms_frame / 1e3) / 1e6, 2), "unit": "Mpix/s",
         "ms": round(ms_frame, 4),
         "workload": "science calibrate + fit + expand + subtract + detect, reference resident"}}
+    if two is not None:
+        variants["two_cameras"] = two
     if args.batch_frames > 0:
         variants["batch"] = batch_leg(args, torch, argus, synth)
     if args.sur_frames > 0:
