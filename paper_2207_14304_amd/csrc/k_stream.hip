@@ -117,33 +117,37 @@ struct CoaddArgs {
 };
 
 // Sort the N values with non-survivors pushed to +inf (odd-even transposition).
+// The inputs are FP32 and their FP64 images order the same way, so the sort
+// runs on the FP32 values and only the middle pair is widened.
 template <int N>
-__device__ __forceinline__ void sort_n(double (&s)[N]) {
+__device__ __forceinline__ void sort_n(float (&s)[N]) {
 #pragma unroll
     for (int pass = 0; pass < N; ++pass) {
 #pragma unroll
         for (int i = pass & 1; i + 1 < N; i += 2) {
-            double lo = fmin(s[i], s[i + 1]), hi = fmax(s[i], s[i + 1]);
+            float lo = fminf(s[i], s[i + 1]), hi = fmaxf(s[i], s[i + 1]);
             s[i] = lo;
             s[i + 1] = hi;
         }
     }
 }
 
+// Median of the survivors (even count: mean of the middle two), in FP64: the
+// sum of two FP32 values and its halving are exact there.
 template <int N>
 __device__ __forceinline__ double median_of(const float (&x)[N], unsigned S, int cnt) {
-    double s[N];
+    float s[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) s[i] = (S >> i & 1u) ? (double)x[i] : __builtin_inf();
+    for (int i = 0; i < N; ++i) s[i] = (S >> i & 1u) ? x[i] : __builtin_inff();
     sort_n<N>(s);
     int lo = (cnt - 1) >> 1, hi = cnt >> 1;
-    double a = 0.0, b = 0.0;
+    float a = 0.f, b = 0.f;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         a = (i == lo) ? s[i] : a;
         b = (i == hi) ? s[i] : b;
     }
-    return 0.5 * (a + b);
+    return 0.5 * ((double)a + (double)b);
 }
 
 template <int N>
