@@ -170,9 +170,9 @@ constexpr int SOLVE_THREADS = 1024;
 // One workgroup of SOLVE_THREADS per solve.  Rows of the packed triangle are
 // addressed through a table of row offsets; a wave walks a row with its
 // lanes on consecutive columns (contiguous in the packed storage).  The
-// factorisation takes one barrier per column: step j updates the trailing
-// matrix with the unscaled column j (a_ic -= a_ij a_cj / a_jj) and scales
-// column j - 1, which no thread reads during step j.
+// factorisation takes one barrier per two columns: a phase applies the
+// unscaled columns j and j + 1 to the trailing matrix in one pass and scales
+// the previous phase's two columns, which no thread reads during the phase.
 // GLT: the factor lives in global memory (a.gtri, for devices whose LDS is too
 // small); otherwise it is in LDS and every access is a plain LDS instruction.
 template <bool GLT>
@@ -183,6 +183,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void fit_solve_kernel(SolveArgs a) {
     __shared__ short rk[256];             // basis, x-power and y-power of row r
     __shared__ unsigned char rp[256], rq[256];
     __shared__ double rdiag[256];         // 1 / L_ii
+    __shared__ double tcol[2][256];       // column j + 1 after column j, by phase parity
     const int n = a.n, tid = threadIdx.x, sol = blockIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int ntri = n * (n + 1) / 2;
@@ -248,31 +249,65 @@ __global__ __launch_bounds__(SOLVE_THREADS) void fit_solve_kernel(SolveArgs a) {
     for (int i = 0; i < NWV; ++i) maxdiag = fmax(maxdiag, red[i]);
     const double tol = (double)n * 0x1p-52 * maxdiag;
     __syncthreads();
-    // right-looking Cholesky, one barrier per column
-    for (int j = 0; j <= n; ++j) {
+    // Right-looking Cholesky, two columns per barrier.  A phase takes columns
+    // j and j + 1 as they stand (updated by every earlier column) and applies
+    // both to the trailing rows and columns c >= j + 2 in one pass:
+    //   t_i = a_i,j+1 - a_ij a_j+1,j / a_jj          (column j + 1 after column j)
+    //   p1  = a_j+1,j+1 - a_j+1,j^2 / a_jj           (its pivot)
+    //   a_ic -= a_ij a_cj / a_jj + t_i t_c / p1      (c <= i)
+    // Every thread forms p1 itself and t_c on the fly from the two columns,
+    // which nobody writes during the phase (t_i goes to tcol), so the phase
+    // needs no barrier inside.  tcol alternates between two buffers: a phase
+    // writes one while the scaling at its start still reads the other.  The columns are scaled to L at the start of
+    // the next phase: L_ij = a_ij / sqrt(a_jj), L_i,j+1 = t_i / sqrt(p1); the
+    // diagonals stay as they are and the substitutions use rdiag = 1 / L_jj.
+    double pv0 = 0.0, pv1 = 0.0;         // pivots of the previous phase
+    for (int j = 0;; j += 2) {
         if (j > 0) {
-            // column j-1: L_i,j-1 = a_i,j-1 / sqrt(a_j-1,j-1) for i > j-1; the
-            // diagonal stays a_j-1,j-1 (every thread reads it here), the
-            // substitutions use rdiag = 1 / L_j-1,j-1
-            const double pv = L[roff[j - 1] + j - 1];
-            const double rs = 1.0 / sqrt(pv);
-            for (int i = j + tid; i < n; i += NT) L[roff[i] + j - 1] *= rs;
-            if (tid == 0) rdiag[j - 1] = rs;
+            const int c0 = j - 2;
+            const double rs0 = 1.0 / sqrt(pv0), rs1 = 1.0 / sqrt(pv1);
+            for (int i = c0 + 1 + tid; i < n; i += NT) L[roff[i] + c0] *= rs0;
+            const double *tp = tcol[((j >> 1) - 1) & 1];
+            for (int i = c0 + 2 + tid; i < n; i += NT) L[roff[i] + c0 + 1] = tp[i] * rs1;
+            if (tid == 0) {
+                rdiag[c0] = rs0;
+                rdiag[c0 + 1] = rs1;
+            }
         }
-        if (j == n) break;
+        if (j >= n) break;
         const double piv = L[roff[j] + j];
         if (!(piv > tol)) {
             if (tid == 0) bad = 1;
             break;
         }
-        const double ip = 1.0 / piv;
-        // trailing update of rows i > j, columns j < c <= i with the unscaled
-        // column j: a wave per row, its lanes on consecutive columns
-        for (int i = j + 1 + wv; i < n; i += NWV) {
-            const double lij = L[roff[i] + j] * ip;
-            double *Li = L + roff[i];
-            for (int c = j + 1 + lane; c <= i; c += 64) Li[c] -= lij * L[roff[c] + j];
+        if (j == n - 1) {                  // odd count: the last column alone
+            if (tid == 0) rdiag[j] = 1.0 / sqrt(piv);
+            break;
         }
+        const double ip = 1.0 / piv;
+        const double r = L[roff[j + 1] + j] * ip;
+        const double p1 = L[roff[j + 1] + j + 1] - L[roff[j + 1] + j] * r;
+        if (!(p1 > tol)) {
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const double ip1 = 1.0 / p1;
+        // rows i >= j + 2, a wave per row, its lanes on consecutive columns
+        double *tw = tcol[(j >> 1) & 1];
+        for (int i = j + 2 + wv; i < n; i += NWV) {
+            double *Li = L + roff[i];
+            const double lij = Li[j];
+            const double ti = Li[j + 1] - lij * r;
+            if (lane == 0) tw[i] = ti;
+            const double a0 = lij * ip, a1 = ti * ip1;
+            for (int c = j + 2 + lane; c <= i; c += 64) {
+                const double lcj = L[roff[c] + j];
+                const double tc = L[roff[c] + j + 1] - lcj * r;
+                Li[c] -= a0 * lcj + a1 * tc;
+            }
+        }
+        pv0 = piv;
+        pv1 = p1;
         __syncthreads();
     }
     __syncthreads();
@@ -494,7 +529,9 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
     int dev_max = 0;
     ARGUS_HIP_CHECK(ctx, hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                                ctx->device));
-    if (lds > (size_t)dev_max) {
+    hipFuncAttributes fattr;
+    ARGUS_HIP_CHECK(ctx, hipFuncGetAttributes(&fattr, (const void *)fit_solve_kernel<false>));
+    if (lds + fattr.sharedSizeBytes > (size_t)dev_max) {
         // factor in global memory (after the sums in the workspace)
         size_t tri = (size_t)sa.n * (sa.n + 1) / 2 * sizeof(double) * n_regions;
         size_t used = (size_t)((char *)(sums + (size_t)n_regions * fa.stride) - (char *)ctx->ws);
