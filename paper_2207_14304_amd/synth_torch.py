@@ -4,8 +4,9 @@ For workloads of many full frames (20 cameras x 61 MPix) the numpy generator
 is too slow; this one draws the same kinds of inputs on the device: uniform
 star positions, power-law fluxes (dN/df ~ f^-1.75 over 1e2..1e6 e-), Moffat
 beta = 3 stars truncated at 8 FWHM and normalised over the truncated disk,
-sky, Poisson + 1.7 e- read noise, half-even rounding to 16-bit ADU.  It
-holds none of the reduction's arithmetic.  Streams come from
+sky, Poisson + 1.7 e- read noise, half-even rounding to 16-bit ADU, the
+same seed giving the same frames bit for bit.  It holds none of the
+reduction's arithmetic.  Streams come from
 numpy SeedSequence(seed) -> torch.Generator seeds.
 """
 from __future__ import annotations
@@ -57,8 +58,19 @@ def render(W, H, xs, ys, fl, fwhm, device, chunk=2048, ell=0.0, theta=0.0):
         Y = yi[:, None, None] + off[None, :, None].to(torch.int64)
         ok = (X >= 0) & (X < W) & (Y >= 0) & (Y < H)
         idx = (Y * W + X)[ok]
-        img.index_add_(0, idx, p[ok])
+        _add_at(img, idx, p[ok])
     return img.view(H, W)
+
+
+def _add_at(img, idx, vals):
+    """img[idx] += vals with repeated indices summed in a fixed order, so that
+    the same seed always gives the same image: a float index_add_ on the device
+    sums colliding contributions with atomics, in whatever order they land."""
+    import torch
+    order = torch.argsort(idx, stable=True)
+    uniq, counts = torch.unique_consecutive(idx[order], return_counts=True)
+    sums = torch.segment_reduce(vals[order], "sum", lengths=counts)
+    img.index_add_(0, uniq, sums)
 
 
 def make_pair(W, H, n_stars, seed, fwhm_sci, ratio=2.0 / 2.6, sky=800.0, scale=1.05,

@@ -215,6 +215,36 @@ def test_training_lowers_the_loss(ctx):
     cnn.close()
 
 
+def test_training_set_and_training_are_deterministic(ctx):
+    """The training set built twice from the same seeds, and a short training
+    from the same initial weights on it, are bit-identical: every reduction on
+    the way has a fixed order and no kernel reads memory it was not given.
+    Between the two passes the freed device memory is overwritten with NaN,
+    so a read of a buffer's unwritten part would show."""
+    import torch
+    from paper_2207_14304_amd import surrogate as sur
+    runs = []
+    for rep in range(2):
+        X, V, T = sur.build_training_set(ctx, 2, 5, n_stars=(800, 1500))
+        tz, mu, sd = sur.standardize(T)
+        cnn = argus.CNN(ctx, max_tiles=8)
+        cnn.set_weights(sur.init_weights(3))
+        sur.train(cnn, X, V, tz, 2, 8, 1e-3, seed=4)
+        torch.cuda.synchronize()
+        runs.append((X.view(torch.int16).cpu(), V.cpu(), T.cpu(), cnn.get_weights().copy()))
+        cnn.close()
+        del X, V, T, tz
+        junk = torch.full((64 << 20,), float("nan"), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+    (x0, v0, t0, w0), (x1, v1, t1, w1) = runs
+    print("training samples", x0.shape[0])
+    assert x0.shape[0] >= 8
+    assert torch.equal(x0, x1) and torch.equal(v0, v1)
+    assert torch.equal(t0.view(torch.int32), t1.view(torch.int32))
+    assert np.array_equal(w0.view(np.int32), w1.view(np.int32))
+
+
 def test_cnn_rejects_bad_shapes(ctx):
     import torch
     cnn = argus.CNN(ctx, max_tiles=2)
