@@ -334,7 +334,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2207_14304_amd import argus, synth

@@ -283,7 +283,8 @@ void argus_batch_destroy(argus_batch *batch);
  * The paper has no learned component.  This one predicts, per tile, the
  * coefficients of the kernel model above (the constant-kernel form of the
  * fit in the difference-imaging step) from paired star stamps; the plain
- * least-squares fit stays the fallback and the judge (chi^2/dof).
+ * least-squares fit stays the fallback and decides by chi^2/dof where the
+ * prediction is kept.
  * Network, shared by every stamp pair of a tile: four 3x3 'same'
  * convolutions (zero padding, cross-correlation) 2 -> 32 -> 32 -> 32 -> 32
  * with bias and ReLU, BF16 weights and activations, FP32 accumulation on

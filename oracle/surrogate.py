@@ -1,6 +1,6 @@
 """FP64 oracle of the learned kernel surrogate (TEST INFRASTRUCTURE ONLY).
 
-The task adds a learned surrogate to the kernel fit: a small CNN that maps a
+A learned surrogate of the kernel fit: a small CNN that maps a
 stack of paired star stamps of one sub-tile to the kernel coefficients, with
 the plain least-squares fit as the fallback.  Written here from its
 definition, in numpy float64:

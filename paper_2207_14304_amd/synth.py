@@ -7,7 +7,7 @@ detection); both the HIP path and the CPU oracle consume what it returns.
 
 Shapes follow the sensor described in the paper (Table 1 and the Image
 Management section: IMX455, 61 MPix, 16-bit, 1.7 e- read noise).  The star
-population, PSF and seeing follow the workload recipes listed in the design doc:
+population, PSF and seeing follow the workloads the benchmark and tests use:
 
 * positions uniform over the frame;
 * fluxes with dN/dm proportional to 10^(0.3 m) between 1e2 and 1e6 e-, i.e.

@@ -6,7 +6,6 @@ the FP64 oracle (coefficients, kernel stamps, difference image) and with the
 oracle's BF16x3 emulation; every variant must reach the plain FP32 form's
 chi^2/dof within 2%."""
 import json
-import os
 
 import numpy as np
 import pytest
@@ -83,9 +82,6 @@ def study(ctx):
                               "coef_max_rel": float(ecerr.max() / np.abs(oco[0]).max()),
                               "coef_rms_rel": float(np.sqrt(np.mean(ecerr ** 2)) / np.abs(oco[0]).max())}
     print(json.dumps(out, indent=1))
-    if os.path.isdir("gpurun_out"):
-        with open(os.path.join("gpurun_out", "precision_study.json"), "w") as fh:
-            json.dump(out, fh, indent=1)
     return out
 
 
