@@ -104,6 +104,35 @@ def test_coadd_parity(ctx, n):
     assert ulp_diff(g_rv, rv).max() <= 4
 
 
+# One or two frames: never more than two survivors, so the clip never runs
+# and every unflagged frame is kept (the mean of one or two values).
+@pytest.mark.parametrize("n", [1, 2])
+def test_coadd_one_or_two_frames(ctx, n):
+    import torch
+    fp = synth.make_pair(131, 97, 80, 29, 2.0, 2.6, n_ref=n, realistic_masters=True,
+                         cosmic_rate=3e-3, n_transients=0)
+    cals, vars_, masks = [], [], []
+    for r in fp.ref_raw:
+        c, v, m = oracle.calibrate(r, fp.dark, fp.flat, fp.bpm)
+        cals.append(c.astype(np.float32))
+        vars_.append(v.astype(np.float32))
+        masks.append(m)
+    rng = np.random.default_rng(4)
+    masks[-1][rng.random(masks[-1].shape) < 0.05] |= oracle.SAT
+    ref, rv, rm, nu = oracle.coadd(cals, vars_, masks, 3.0, 5)
+    usable = sum(((m & (oracle.BAD | oracle.SAT)) == 0).astype(np.int64) for m in masks)
+    assert np.array_equal(nu, usable)
+    H, W = cals[0].shape
+    outs = [empty((H, W), torch.float32), empty((H, W), torch.float32),
+            empty((H, W), torch.uint8), empty((H, W), torch.uint8)]
+    ctx.coadd([dev(c) for c in cals], [dev(v) for v in vars_], [dev(m) for m in masks], 3.0, 5,
+              *outs)
+    g_ref, g_rv, g_rm, g_nu = (host(x) for x in outs)
+    assert np.array_equal(g_nu, nu) and np.array_equal(g_rm, rm)
+    assert ulp_diff(g_ref, ref).max() <= 4
+    assert ulp_diff(g_rv, rv).max() <= 4
+
+
 # Fused calibration + coadd: bit-identical to the two calls (odd width and a
 # padded pitch take the scalar path at row ends), and within the coadd bars
 # of the oracle's calibrate-then-coadd.
