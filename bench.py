@@ -244,7 +244,7 @@ def surrogate_leg(args, torch, argus):
     from paper_2207_14304_amd import surrogate as sur
     ctx = argus.Context(0)
     t0 = time.perf_counter()
-    X, V, T = sur.build_training_set(ctx, args.sur_frames, 1, n_stars=(3000, 20000))
+    X, V, T = sur.build_training_set(ctx, args.sur_frames, 1, n_stars=(3000, 20000), log=log)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     Ts, mu, sd = sur.standardize(T)
@@ -258,6 +258,7 @@ def surrogate_leg(args, torch, argus):
     for ep in range(args.sur_epochs):
         lr = 2e-3 if ep < 0.7 * args.sur_epochs else 4e-4
         steps += len(sur.train(cnn, X, V, Ts, 1, 32, lr, seed=100 + ep))
+        log(f"surrogate: epoch {ep} queued ({n} samples)")
     e1.record()
     torch.cuda.synchronize()
     train_ms = e0.elapsed_time(e1)

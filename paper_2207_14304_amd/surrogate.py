@@ -123,7 +123,7 @@ def extract(ctx, frame_planes, tiles=TILES, snr_min=SNR_MIN):
 
 
 def build_training_set(ctx, n_frames, seed, W=1024, H=1024, n_stars=(300, 4000), tiles=TILES,
-                       noise_free_targets=True):
+                       noise_free_targets=True, log=None):
     """Samples (X bf16 [N][64][961][2], valid u8 [N][64], target f32 [N][31]) from
     n_frames seeded frame pairs.  The inputs are stamps of the noisy frames; the
     targets are the plain per-tile fit's kernel coefficients, by default of the
@@ -145,6 +145,8 @@ def build_training_set(ctx, n_frames, seed, W=1024, H=1024, n_stars=(300, 4000),
         Xs.append(X[keep])
         Vs.append(valid[keep])
         Ts.append(fits.coeffs[keep, :NB].float())
+        if log and (f + 1) % 500 == 0:
+            log(f"training set: {f + 1} of {n_frames} frames")
     return torch.cat(Xs), torch.cat(Vs), torch.cat(Ts)
 
 
