@@ -67,6 +67,8 @@ def _add_at(img, idx, vals):
     the same seed always gives the same image: a float index_add_ on the device
     sums colliding contributions with atomics, in whatever order they land."""
     import torch
+    if img.numel() < (1 << 31):
+        idx = idx.to(torch.int32)          # narrower keys sort faster
     order = torch.argsort(idx, stable=True)
     uniq, counts = torch.unique_consecutive(idx[order], return_counts=True)
     sums = torch.segment_reduce(vals[order], "sum", lengths=counts)
