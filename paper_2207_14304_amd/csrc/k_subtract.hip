@@ -212,8 +212,23 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
 #pragma unroll
                 for (int i = 0; i < PXT; ++i) foot[i] |= Mr[(ly + vv) * BW + lx0 + i];
             }
-            // background polynomial of this pixel's solve
+            // background polynomial of this pixel's solve, folded along the row
+            // (yt fixed) into x-coefficients: bg = sum_p cx[p] xt^p with
+            // cx[p] = sum_q bg_pq yt^q (monomials p outer, q inner)
             const float *bgp = a.bg + (size_t)reg * ((a.Dbg + 1) * (a.Dbg + 2) / 2);
+            double cx[ARGUS_MAX_D + 1];
+            {
+                int mi = 0;
+#pragma unroll
+                for (int pp = 0; pp <= ARGUS_MAX_D; ++pp) {
+                    double c = 0.0, yq = 1.0;
+                    for (int qq = 0; pp <= a.Dbg && qq <= a.Dbg - pp; ++qq, ++mi) {
+                        c += (double)bgp[mi] * yq;
+                        yq *= ytd;
+                    }
+                    cx[pp] = c;
+                }
+            }
             float outd[PXT], outv[PXT];
             uint8_t outm[PXT];
             const int64_t orow = (int64_t)Y * P;
@@ -228,18 +243,10 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
                                  ((!edge && foot[i]) ? ARGUS_FOOT : 0u);
                     outm[i] = dm;
                     if (dm == 0) {
-                        double xd = (double)X * a.sx - (a.sx != 0.0 ? 1.0 : 0.0);
-                        double bgv = 0.0;
-                        int mi = 0;
-                        for (int pp = 0; pp <= a.Dbg; ++pp) {
-                            double xp = 1.0;
-                            for (int e = 0; e < pp; ++e) xp *= xd;
-                            double yq = 1.0;
-                            for (int qq2 = 0; qq2 <= a.Dbg - pp; ++qq2, ++mi) {
-                                bgv += (double)bgp[mi] * xp * yq;
-                                yq *= ytd;
-                            }
-                        }
+                        const double xd = (double)X * a.sx - (a.sx != 0.0 ? 1.0 : 0.0);
+                        double bgv = cx[ARGUS_MAX_D];
+#pragma unroll
+                        for (int pp = ARGUS_MAX_D - 1; pp >= 0; --pp) bgv = bgv * xd + cx[pp];
                         const float s = a.sci[o], sv = a.svar[o];
                         const float dval = s - (float)((double)m[i] + bgv);
                         outd[i] = dval;
