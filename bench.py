@@ -38,8 +38,9 @@ def parse():
     p.add_argument("--height", type=int, default=6388)
     p.add_argument("--stars", type=int, default=60000)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--two-cameras", type=int, default=1,
-                   help="also time two cameras' steps on two streams (0: skip)")
+    p.add_argument("--two-cameras", type=int, default=0,
+                   help="also time two cameras' steps on two streams (its launches overlap, "
+                        "so a kernel trace of such a run mixes concurrent kernels)")
     p.add_argument("--cpu-crop", type=int, default=1024)
     p.add_argument("--batch-frames", type=int, default=20)
     p.add_argument("--batch-cutouts", type=int, default=4000)
