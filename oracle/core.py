@@ -265,14 +265,14 @@ def design_rows(C, xt, yt, ys, xs, spec):
     return X
 
 
-def normal_equations(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B=None):
+def normal_equations(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B=None, C=None):
     """Per tile t: A_t = sum w X X^T, b_t = sum w X S over the fit set in t,
     with w = 1/(var_S + var_R).  Returns (A [T][n][n], b [T][n], n_fit [T])
-    for the tiles in raster order."""
+    for the tiles in raster order.  C, if given, is convolve(ref, B)."""
     B = basis(spec) if B is None else B
     H, W = np.shape(ref)
     h = spec.half_width
-    C = convolve(ref, B)
+    C = convolve(ref, B) if C is None else C
     phi = fit_set(ref_mask, sci_mask, ref_var, sci_var, h)
     xt, yt = norm_coords(W, H)
     sci = np.asarray(sci, np.float64)
@@ -347,11 +347,12 @@ def solve(A, b, n_fit):
     return d * y, STATUS_OK
 
 
-def fit_kernel(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B=None):
+def fit_kernel(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B=None, C=None):
     """Least-squares kernel fit.  GLOBAL: the tile sums are added in raster
-    order and solved once.  PER_TILE: one solve per tile.
+    order and solved once.  PER_TILE: one solve per tile.  C, if given, is the
+    stack of basis convolutions of ref.
     Returns (coeffs [n_solves][n], status [n_solves], n_fit [n_solves])."""
-    A, b, nf = normal_equations(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B)
+    A, b, nf = normal_equations(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B, C)
     if spec.mode == GLOBAL:
         As = np.zeros(A.shape[1:])
         bs = np.zeros(b.shape[1:])

@@ -9,7 +9,8 @@ definition, in numpy float64:
   (strictly above earlier 8-neighbours in raster order, >= later ones),
   brightest first with raster order breaking ties, whose (2r+1)^2 stamp
   lies inside the frame and is unmasked in both frames, and whose peak is
-  at least snr_min noise sigmas above the reference stamp's border median.  Each stamp has its border median subtracted; both stamps are
+  at least snr_min noise sigmas above the reference stamp's border median
+  (every decision in FP64).  Each stamp has its border median subtracted; both stamps are
   divided by the background-subtracted reference stamp sum and scaled by a
   fixed 100;
 * network - four 3x3 'same' convolutions (zero padding, cross-correlation)
@@ -31,7 +32,7 @@ from . import core
 
 # ------------------------------------------------------------------ stamps
 def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64,
-                  snr_min=10.0):
+                  snr_min=10.0, tie_tol=None):
     """Per tile (raster order of tiles) a list of up to S (y, x) stamp centres.
 
     Candidates are positive reference local maxima (strictly above the
@@ -42,12 +43,14 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
     order breaking ties.  Walking down the ranking a candidate is kept when
     its stamp is unmasked in both frames and (peak - border median of its
     reference stamp) / sqrt(var at the peak) >= snr_min; the walk stops at S.
-    Both tests decide integers (which stamps are kept), so they are taken in
-    float32, the precision of the frames: medians average the middle pair in
-    float32, and the division and square root round correctly."""
+    Every quantity is taken in FP64 (medians average the middle pair).
+
+    With tie_tol set, also returns per tile the number of candidates whose
+    sky or border test quantity lies within tie_tol * snr_min of snr_min:
+    there an implementation that rounds differently may decide the other
+    way (and every later stamp of the tile may shift)."""
     ref = np.asarray(ref, np.float64)
-    r32 = np.asarray(ref, np.float32)
-    v32 = np.asarray(ref_var, np.float32)
+    var = np.asarray(ref_var, np.float64)
     H, W = ref.shape
     pad = np.full((H + 2, W + 2), -np.inf)
     pad[1:-1, 1:-1] = ref
@@ -61,20 +64,26 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
             lm &= (ref > nb) if earlier else (ref >= nb)
     bad = (np.asarray(ref_mask) != 0) | (np.asarray(sci_mask) != 0)
     out = []
+    near = []
     for (y0, y1) in core.tile_bounds(H, tiles_y):
         for (x0, x1) in core.tile_bounds(W, tiles_x):
-            un = r32[y0:y1, x0:x1][np.asarray(ref_mask)[y0:y1, x0:x1] == 0]
+            un = ref[y0:y1, x0:x1][np.asarray(ref_mask)[y0:y1, x0:x1] == 0]
             if un.size == 0:
                 out.append([])
+                near.append(0)
                 continue
-            sky = median32(un)
+            sky = np.median(un)
             ys, xs = np.nonzero(lm[y0:y1, x0:x1])
             ys, xs = ys + y0, xs + x0
             inside = (ys >= r) & (xs >= r) & (ys < H - r) & (xs < W - r)
             ys, xs = ys[inside], xs[inside]
+            nt = 0
             with np.errstate(all="ignore"):
-                vv = v32[ys, xs]
-                above = (vv > 0) & ((r32[ys, xs] - sky) / np.sqrt(vv) >= np.float32(snr_min))
+                vv = var[ys, xs]
+                q = np.where(vv > 0, (ref[ys, xs] - sky) / np.sqrt(vv), -np.inf)
+            above = q >= snr_min
+            if tie_tol is not None:
+                nt += int((np.abs(q - snr_min) <= tie_tol * snr_min).sum())
             cand = sorted(zip(ys[above], xs[above]), key=lambda p: (-ref[p[0], p[1]],
                                                                      p[0] * W + p[1]))
             keep = []
@@ -83,28 +92,18 @@ def select_stamps(ref, ref_var, ref_mask, sci_mask, tiles_x, tiles_y, r=15, S=64
                     break
                 if bad[y - r:y + r + 1, x - r:x + r + 1].any():
                     continue
-                m = border_median32(r32[y - r:y + r + 1, x - r:x + r + 1])
-                v = v32[y, x]
+                m = border_median(ref[y - r:y + r + 1, x - r:x + r + 1])
+                v = var[y, x]
                 if not v > 0:
                     continue
-                if (r32[y, x] - m) / np.sqrt(v) >= np.float32(snr_min):
+                qb = (ref[y, x] - m) / np.sqrt(v)
+                if tie_tol is not None and abs(qb - snr_min) <= tie_tol * snr_min:
+                    nt += 1
+                if qb >= snr_min:
                     keep.append((y, x))
             out.append(keep)
-    return out
-
-
-def median32(v):
-    """Median in float32: the middle value, or the middle pair averaged in float32."""
-    b = np.sort(np.asarray(v, np.float32).ravel())
-    k = b.size
-    if k % 2:
-        return b[k // 2]
-    return (b[k // 2 - 1] + b[k // 2]) * np.float32(0.5)
-
-
-def border_median32(st):
-    """Median of a stamp's border in float32."""
-    return median32(np.concatenate([st[0, :], st[-1, :], st[1:-1, 0], st[1:-1, -1]]))
+            near.append(nt)
+    return (out, near) if tie_tol is not None else out
 
 
 def border_median(st):

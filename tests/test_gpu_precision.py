@@ -15,7 +15,8 @@ from oracle import precision
 from paper_2207_14304_amd import argus, synth
 from gpu_util import dev, host, empty
 
-pytestmark = pytest.mark.gpu
+# the oracle fit, subtraction and split emulation of the 1024^2 study take about a minute
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 
 @pytest.fixture(scope="module")
@@ -37,10 +38,11 @@ def study(ctx):
     f = lambda a: a.astype(np.float32)
     planes = (f(cr), f(vr), mr, f(cs), f(vs), ms)
     ospec = oracle.KernelSpec(half_width=7, spatial_degree=2, bg_degree=2, tiles_x=16, tiles_y=16)
-    oco, ost, onf = oracle.fit_kernel(*planes, ospec)
+    C = oracle.convolve(planes[0], oracle.basis(ospec))          # shared by the two fits
+    oco, ost, onf = oracle.fit_kernel(*planes, ospec, C=C)
     ostamps, obg = oracle.expand_kernel(oco, ospec)
     oD, oV, oM, oc2, onc = oracle.subtract(ostamps, obg, *planes, ospec)
-    eco, est, _ = precision.fit_kernel_bf16x3(*planes, ospec)
+    eco, est, _ = precision.fit_kernel_bf16x3(*planes, ospec, C=C)
     out = {"oracle": {"chi2_dof": float(oc2[0] / (onc[0] - 192))}}
     dplanes = [dev(p) for p in planes]
     H, W = cr.shape
@@ -109,18 +111,17 @@ def test_variants_reach_plain_chi2(study):
     assert abs(study["oracle"]["chi2_dof"] / base - 1.0) <= 1e-5
 
 
-def test_bf16x3_error_within_emulated_bound(study):
-    """The emulation splits the weighted design matrix into BF16 hi/lo parts
-    and accumulates the whole tile's Gram in FP32; the GPU splits the moment
-    operands the same way but flushes each 64-pixel row sum into FP64, so its
-    coefficient error is bounded by the emulated one (measured: about 45x
-    below it)."""
+def test_bf16x3_error_matches_the_emulated_split(study):
+    """The oracle's emulation of the split (operands c_k and w xt^a c_l split
+    into bf16 hi/lo, three products, 64-pixel FP32 row sums flushed into FP64)
+    predicts the GPU's coefficient error: the two RMS errors agree within a
+    factor of 2 either way."""
     g = study["bf16x3"]["coef_rms_rel"]
     e = study["bf16x3_emulated"]["coef_rms_rel"]
     assert study["bf16x3_emulated"]["status"] == 0
-    assert g <= e, (g, e)
-    # BF16x3 sits at the FP32 form's difference bar (measured 1.0e-4 sigma
-    # RMS); its own bar is 2e-4 sigma RMS, and its chi^2/dof equals the
-    # plain form's (test_variants_reach_plain_chi2)
+    assert 0.5 <= g / e <= 2.0, (g, e)
+
+
+def test_bf16x3_difference_within_bar(study):
     s = study["bf16x3"]
-    assert s["diff_rms_sigma"] <= 2e-4 and s["diff_max_sigma"] <= 1e-2
+    assert s["diff_rms_sigma"] <= 1e-4 and s["diff_max_sigma"] <= 1e-2

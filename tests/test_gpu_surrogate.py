@@ -117,7 +117,9 @@ def test_extract_stamps_match_oracle(ctx):
     mr[rng.random(mr.shape) < 2e-4] |= oracle.SAT
     ms[rng.random(ms.shape) < 2e-4] |= oracle.BAD
     TX, TY = 3, 2
-    cents = sg.select_stamps(cr, vr, mr, ms, TX, TY, r=R, S=S, snr_min=10.0)
+    # the oracle decides in FP64 and the kernel in FP32: tiles where a
+    # candidate's test quantity lies within 1e-5 of the threshold may differ
+    cents, near = sg.select_stamps(cr, vr, mr, ms, TX, TY, r=R, S=S, snr_min=10.0, tie_tol=1e-5)
     Xo, vo = sg.make_stamps(cr, cs, cents, r=R, S=S)
     T = TX * TY
     X = torch.full((T, S, NPX, 2), 7.0, dtype=torch.bfloat16, device="cuda")
@@ -126,11 +128,14 @@ def test_extract_stamps_match_oracle(ctx):
     ctx.extract_stamps(dev(cr), dev(vr), dev(mr), dev(cs), dev(ms), TX, TY, 10.0, X, valid, ovf)
     gv = host(valid)
     assert int(host(ovf)[0]) == 0
-    assert np.array_equal(gv, vo.astype(np.uint8))
+    print(f"near-threshold candidates per tile: {near}")
+    clear = np.array(near) == 0
+    assert clear.sum() >= T - 1                      # expected: none near the threshold
+    assert np.array_equal(gv[clear], vo.astype(np.uint8)[clear])
     assert 0 < gv.sum() < T * S                      # some tiles are full, some are not
     gX = X.float().cpu().numpy().reshape(T, S, 31, 31, 2).transpose(0, 1, 4, 2, 3)
     tol = 2.0 ** -7 * np.abs(Xo) + 1e-6 * np.abs(Xo).max()
-    assert np.all(np.abs(gX - Xo) <= tol)
+    assert np.all(np.abs(gX - Xo)[clear] <= tol[clear])
 
 
 # --------------------------------------------------------------- network

@@ -98,9 +98,10 @@ def test_coadd_even_median_and_survivor_floor():
     # only one sample would survive: keep the current set
     ref, rv, rm, nu = _stack([0, 50, 100, 150, 200.0], [1.0] * 5)
     assert nu[0, 0] == 5 and ref[0, 0] == 100.0
-    # two survivors are allowed
+    # two survivors are allowed: median 100, sigma 1 rejects 0, 0 and 200,
+    # which leaves exactly two, and the next pass stops at |S| <= 2
     ref, rv, rm, nu = _stack([0, 0, 100, 100, 200.0], [1.0] * 5)
-    assert nu[0, 0] == 5 or (nu[0, 0] == 2 and ref[0, 0] == 100.0)
+    assert nu[0, 0] == 2 and ref[0, 0] == 100.0 and rv[0, 0] == 0.5
 
 
 def test_coadd_nodata_and_sat():
@@ -511,6 +512,81 @@ def test_psf_flux_closed_form():
     assert top["flux_err"] == pytest.approx(math.sqrt(37.0 / (P * P).sum()), rel=1e-12)
 
 
+def _isolated(xs, ys, i, dmin=20.0, chebyshev=False):
+    dx = np.abs(np.asarray(xs, float) - xs[i])
+    dy = np.abs(np.asarray(ys, float) - ys[i])
+    d = np.maximum(dx, dy) if chebyshev else np.hypot(dx, dy)
+    d[i] = np.inf
+    return d.min() > dmin
+
+
+@pytest.mark.slow
+def test_transient_flux_pulls_over_50_seeds():
+    """Injected-transient protocol of the Transient Alerts section (Fig. 3),
+    reduced to the steps it pins: the subtraction with a known kernel and the
+    detection's PSF flux and its error.  Per seed, a noise-free reference
+    star field R (FWHM 2.0) is convolved with a kernel drawn in the basis
+    span, a background is added, and 12 point transients of the exact science
+    PSF are placed at integer pixels; the science frame is one Poisson +
+    read-noise exposure of that.  Subtracting with the true kernel leaves
+    D = transients + noise, and the science variance passed in is the
+    expected one (a variance taken from the observed counts correlates the
+    weights with the noise and biases the PSF flux low by about
+    sum(P) / sqrt(V sum(P^2)), 0.16 sigma on an 800 e- sky).  Over 50 seeds the
+    pulls (flux - f) / flux_err of isolated transients must then be standard
+    normal: mean within 3/sqrt(N) of 0 and standard deviation 1 +- 0.1
+    (transients whose 15x15 windows overlap another's are left out)."""
+    W = H = 224
+    r = 7
+    spec = oracle.KernelSpec(half_width=r, **SPEC31)
+    B = oracle.basis(spec)
+    P = synth.psf_image(r, 2.6)
+    pulls = []
+    for seed in range(50):
+        rng = np.random.default_rng(7000 + seed)
+        n = 120
+        sx, sy = rng.uniform(0, W, n), rng.uniform(0, H, n)
+        sf = synth.draw_fluxes(rng, n, 1e2, 1e5)
+        R = 800.0 + synth.render_scene(W, H, sx, sy, sf, lambda x: np.full(np.shape(x), 2.0))
+        a = np.zeros(31)
+        a[0] = 1.05
+        a[1:] = 0.003 * rng.standard_normal(30)
+        K = np.tensordot(a, B, axes=1)
+        E = oracle.convolve(R, K) - 40.0
+        tx = rng.integers(24, W - 24, 12)
+        ty = rng.integers(24, H - 24, 12)
+        tf = np.exp(rng.uniform(np.log(1e3), np.log(1e5), 12))
+        for x, y, f in zip(tx, ty, tf):
+            E[y - r:y + r + 1, x - r:x + r + 1] += f * P
+        E = np.nan_to_num(E, nan=800.0)                  # border rows (masked EDGE anyway)
+        assert E.min() > 0
+        S = rng.poisson(E) + rng.normal(0.0, 1.7, E.shape)
+        Sv = E + 1.7 ** 2
+        z = np.zeros((H, W), np.uint8)
+        D, V, dm, _, _ = oracle.subtract(K[None], np.array([-40.0]), R, np.zeros((H, W)), z, S, Sv,
+                                         z, spec)
+        _, _, c = oracle.detect(D, V, dm, 5.0, P)
+        for i, (x, y, f) in enumerate(zip(tx, ty, tf)):
+            if not _isolated(tx, ty, i, 2 * r, chebyshev=True):   # windows do not overlap
+                continue
+            # the estimator at the injected pixel, whether or not it peaks there
+            q = (P * P / V[y - r:y + r + 1, x - r:x + r + 1]).sum()
+            fh = (P * D[y - r:y + r + 1, x - r:x + r + 1] / V[y - r:y + r + 1, x - r:x + r + 1]).sum() / q
+            pulls.append((fh - f) * math.sqrt(q))
+            near = c[(np.abs(c["x"] - x) <= 1) & (np.abs(c["y"] - y) <= 1)]
+            if f * P[r, r] / math.sqrt(V[y, x]) >= 7:
+                assert len(near) >= 1, (seed, x, y, f)
+            hit = near[(near["x"] == x) & (near["y"] == y)]
+            if len(hit):
+                assert hit[0]["flux"] == pytest.approx(fh, rel=1e-12)
+                assert hit[0]["flux_err"] == pytest.approx(q ** -0.5, rel=1e-12)
+    pulls = np.array(pulls)
+    print(f"pulls: n {pulls.size} mean {pulls.mean():.3f} std {pulls.std():.3f}")
+    assert pulls.size >= 400
+    assert abs(pulls.mean()) <= 3.0 / math.sqrt(pulls.size), pulls.mean()
+    assert abs(pulls.std() - 1.0) <= 0.1, pulls.std()
+
+
 @pytest.mark.parametrize("seed", [101, 102])
 def test_injected_transient_recovery(seed):
     """Fig. 3's protocol at reduced size: point transients injected into the
@@ -526,8 +602,9 @@ def test_injected_transient_recovery(seed):
     P = synth.psf_image(7, 2.6)
     _, _, c = oracle.detect(D, V, dm, 5.0, P)
     pulls = []
-    for x, y, f in zip(fp.trans_x, fp.trans_y, fp.trans_f):
-        if dm[y, x] != 0:
+    for i, (x, y, f) in enumerate(zip(fp.trans_x, fp.trans_y, fp.trans_f)):
+        # masked pixels and blends (another transient within 20 px) are not pinned
+        if dm[y, x] != 0 or not _isolated(fp.trans_x, fp.trans_y, i):
             continue
         expected = f * P[7, 7] / math.sqrt(V[y, x])
         near = c[(np.abs(c["x"] - x) <= 1) & (np.abs(c["y"] - y) <= 1)]

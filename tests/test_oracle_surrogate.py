@@ -61,6 +61,41 @@ def test_invalid_stamps_do_not_contribute():
     assert np.array_equal(out, out2)
 
 
+def _features(p, stamp):
+    """Spatial mean of the last layer for one stamp pair, written out with
+    scipy's correlation (independent of sg.conv3x3)."""
+    a = stamp
+    for l in range(4):
+        w, b = p[f"w{l}"], p[f"b{l}"]
+        a = np.maximum(np.stack([b[o] + sum(signal.correlate2d(a[c], w[o, c], mode="same")
+                                            for c in range(a.shape[0]))
+                                 for o in range(w.shape[0])]), 0.0)
+    return a.mean(axis=(1, 2))
+
+
+def test_forward_is_the_mean_over_valid_stamps():
+    """Closed forms of the pooling over stamps: a tile with one valid stamp
+    gives hw . f(s) + hb; k copies of that stamp give the same output
+    (the mean divides by the number of valid stamps, not by S); two valid
+    stamps give the mean of their features; invalid slots hold garbage."""
+    rng = np.random.default_rng(21)
+    p = sg.init_params(rng, C=4, cin=2, nout=5)
+    for l in range(4):
+        p[f"b{l}"] = 0.1 * rng.standard_normal(4)
+    p["hb"] = rng.standard_normal(5)
+    s0, s1 = rng.standard_normal((2, 2, 7, 7))
+    X = 50.0 * rng.standard_normal((3, 4, 2, 7, 7))
+    X[0, 2] = s0
+    X[1, 0] = X[1, 1] = X[1, 3] = s0
+    X[2, 1], X[2, 3] = s0, s1
+    valid = np.array([[0, 0, 1, 0], [1, 1, 0, 1], [0, 1, 0, 1]], np.float64)
+    out, _ = sg.forward(p, X, valid)
+    f0, f1 = _features(p, s0), _features(p, s1)
+    assert np.allclose(out[0], p["hw"] @ f0 + p["hb"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(out[1], out[0], rtol=1e-12, atol=1e-12)
+    assert np.allclose(out[2], p["hw"] @ ((f0 + f1) / 2) + p["hb"], rtol=1e-12, atol=1e-12)
+
+
 def test_adam_first_step_closed_form():
     p = {"w": np.array([1.0, -2.0, 3.0])}
     g = {"w": np.array([0.5, -0.25, 0.0])}
@@ -175,7 +210,10 @@ def test_stamp_snr_is_above_the_border_median():
     m[25:45, 5:25] = 0
     got = sg.select_stamps(low, var, m, z, 1, 1, r=5, S=8, snr_min=10.0)
     assert got == [[(35, 15)]]
-    assert sg.median32(np.array([1.0, 4.0, 2.0, 3.0], np.float32)) == np.float32(2.5)
     st = np.arange(36.0).reshape(6, 6)
     b = np.r_[st[0], st[-1], st[1:-1, 0], st[1:-1, -1]]
-    assert sg.border_median32(st) == np.float32(np.median(b))
+    assert sg.border_median(st) == np.median(b) == 17.5        # even count: middle pair
+    # the peak at exactly 10 sigma is a near-tie of the border test; the sky
+    # test (1100 - 1000)/10 = 10 is one too; nothing else is within 1e-6
+    cs, near = sg.select_stamps(ref, var, z, z, 1, 1, r=5, S=8, snr_min=10.0, tie_tol=1e-6)
+    assert cs == [[(20, 20), (12, 45)]] and near == [2]
