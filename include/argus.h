@@ -167,7 +167,11 @@ int argus_calibrate_coadd(argus_ctx *ctx, argus_dims dims, int n_frames,
                           float kappa, int max_iter, float *ref, float *ref_var,
                           uint8_t *ref_mask, uint8_t *n_used);
 
-/* Number of unknowns per solve and number of solves for a spec. */
+/* Number of unknowns per solve and number of solves for a spec (the kernel
+ * model of the direct subtraction, Transient Alerts / Table 2): n as given
+ * above the argus_kernel_spec type; one solve for ARGUS_FIT_GLOBAL,
+ * tiles_x * tiles_y for ARGUS_FIT_PER_TILE.  Either output is nullable;
+ * ARGUS_EINVAL or ARGUS_ESHAPE for an invalid spec. */
 int argus_kernel_dims(const argus_kernel_spec *spec, int *n_unknowns, int *n_solves);
 
 /* ---- kernel fit (direct subtraction of Transient Alerts / Table 2) ------
@@ -178,19 +182,29 @@ int argus_kernel_dims(const argus_kernel_spec *spec, int *n_unknowns, int *n_sol
  * Normal equations are accumulated per tile (FP32 products, FP64 sums),
  * added in FP64 (all tiles for GLOBAL), Jacobi-scaled and Cholesky-solved in
  * FP64 on the GPU.  Outputs (device): coeffs f64 [n_solves][n] (NaN where the
- * solve failed), n_fit i64 [n_solves] (nullable), status i32 [n_solves]
- * (ARGUS_OK, ARGUS_ESINGULAR or ARGUS_ETOOFEW). */
+ * solve failed), chi2 f64 [n_solves] (nullable), n_fit i64 [n_solves]
+ * (nullable), status i32 [n_solves] (ARGUS_OK, ARGUS_ESINGULAR or
+ * ARGUS_ETOOFEW).  chi2 = sum over the fit set of w (S - X a)^2, taken as a
+ * second pass over the residuals: the solution is expanded into stamps and
+ * the subtraction below is run without writing its images (the residual of
+ * a fit pixel is exactly its difference D); NaN where the solve failed; the
+ * degrees of freedom are n_fit - n.  Requesting chi2 costs one pass of
+ * argus_subtract and a per-context stamp buffer, allocated on first use
+ * (ARGUS_EBUSY if that first use is under stream capture). */
 int argus_fit_kernel(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
                      const float *ref, const float *ref_var, const uint8_t *ref_mask,
                      const float *sci, const float *sci_var, const uint8_t *sci_mask,
-                     double *coeffs, int64_t *n_fit, int32_t *status);
+                     double *coeffs, double *chi2, int64_t *n_fit, int32_t *status);
 
-/* K_m = sum_k a_{k nP + m} B_k and bg_m = a_{nb nP + m}, evaluated in FP64.
+/* ---- kernel expansion (the kernel model of the direct subtraction,
+ * Transient Alerts / Table 2; Alard 2000's normalised basis) ---------------
+ * K_m = sum_k a_{k nP + m} B_k and bg_m = a_{nb nP + m}, evaluated in FP64.
  * stamps f32 [n_solves][nP][2h+1][2h+1], bg f32 [n_solves][nPbg]. */
 int argus_expand_kernel(argus_ctx *ctx, const argus_kernel_spec *spec,
                         const double *coeffs, float *stamps, float *bg);
 
-/* ---- PSF-matched convolution and subtraction ------------------------------
+/* ---- PSF-matched convolution and subtraction (direct image subtraction,
+ * Transient Alerts section; Table 2) ----------------------------------------
  * Per pixel p, with K_p = sum_m P_m(p) K_m of the solve owning p:
  *   D = S - (sum_{u,v} K_p(u,v) R(x-u, y-v) + sum_m bg_m P_m(p))
  *   V = var_S + sum_{u,v} K_p(u,v)^2 var_R(x-u, y-v)

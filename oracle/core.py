@@ -62,7 +62,7 @@ def calibrate(raw, dark, flat, bpm, gain=1.0, read_noise=1.7, sat_adu=65535):
 # Reference coadd: iterative kappa-sigma clip about the median, sigma taken
 # from the noise model (Deep Coaddition / Transient Alerts sections).
 # ---------------------------------------------------------------------------
-def coadd(cals, vars_, masks, kappa=3.0, max_iter=5):
+def coadd(cals, vars_, masks, kappa=3.0, max_iter=5, return_margin=False):
     """Clipped mean of n registered calibrated frames, per pixel.
 
     Reading: a sigma estimated from the same five samples can never reject one
@@ -80,12 +80,18 @@ def coadd(cals, vars_, masks, kappa=3.0, max_iter=5):
       ref = mean(x_S), ref_var = sum(v_S)/|S|^2, n_used = |S|
       ref_mask: NODATA where S starts empty (ref = ref_var = 0);
                 SAT where any input frame is SAT.
+
+    With return_margin, also returns per pixel the smallest relative distance
+    | |x_i - c| - kappa sigma | / (kappa sigma) over the samples and passes
+    the clip evaluated (inf where it never ran): where it is tiny, inputs
+    that differ by rounding may be clipped differently.
     """
     x = np.stack([np.asarray(c, np.float64) for c in cals])
     v = np.stack([np.asarray(c, np.float64) for c in vars_])
     m = np.stack([np.asarray(c, np.uint8) for c in masks])
     S = (m & (BAD | SAT)) == 0
     active = np.ones(x.shape[1:], bool)
+    margin = np.full(x.shape[1:], np.inf)
     with np.errstate(all="ignore"):
         for _ in range(max_iter):
             cnt = S.sum(0)
@@ -94,7 +100,12 @@ def coadd(cals, vars_, masks, kappa=3.0, max_iter=5):
                 break
             c = np.nanmedian(np.where(S, x, np.nan), axis=0)
             s2 = np.nanmedian(np.where(S, v, np.nan), axis=0)
-            rej = S & (np.abs(x - c) > kappa * np.sqrt(s2)) & active
+            ks = kappa * np.sqrt(s2)
+            if return_margin:
+                rel = np.abs(np.abs(x - c) - ks) / ks
+                rel = np.where(S & active, rel, np.inf).min(0)
+                margin = np.minimum(margin, np.where(np.isnan(rel), 0.0, rel))
+            rej = S & (np.abs(x - c) > ks) & active
             nrej = rej.sum(0)
             active &= nrej > 0
             active &= (cnt - nrej) >= 2
@@ -104,6 +115,8 @@ def coadd(cals, vars_, masks, kappa=3.0, max_iter=5):
         ref_var = np.where(cnt > 0, np.where(S, v, 0.0).sum(0) / np.maximum(cnt, 1) ** 2, 0.0)
     ref_mask = np.where(cnt == 0, NODATA, 0).astype(np.uint8)
     ref_mask |= np.where(((m & SAT) != 0).any(0), SAT, 0).astype(np.uint8)
+    if return_margin:
+        return ref, ref_var, ref_mask, cnt.astype(np.uint8), margin
     return ref, ref_var, ref_mask, cnt.astype(np.uint8)
 
 

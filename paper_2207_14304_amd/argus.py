@@ -100,7 +100,7 @@ def load(path: str = LIB_PATH):
     lib.argus_calibrate_coadd.argtypes = [vp, Dims, C.c_int, vp, vp, vp, vp, f32, f32, C.c_uint16,
                                           f32, C.c_int, vp, vp, vp, vp]
     lib.argus_kernel_dims.argtypes = [C.POINTER(KernelSpec), C.POINTER(C.c_int), C.POINTER(C.c_int)]
-    lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 9
+    lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 10
     lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
     lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 15
     lib.argus_detect.argtypes = [vp, Dims, vp, vp, vp, f32, vp, C.c_int, vp, vp, vp, i32, vp]
@@ -241,14 +241,15 @@ class Context:
             _ptr(ref_mask, torch.uint8), _ptr(n_used, torch.uint8)))
 
     def fit_kernel(self, spec, ref, ref_var, ref_mask, sci, sci_var, sci_mask, coeffs, n_fit,
-                   status):
+                   status, chi2=None):
         torch = self._torch
         self._bind()
         self._check(self.lib.argus_fit_kernel(
             self.h, _dims(ref), C.byref(spec), _ptr(ref, torch.float32),
             _ptr(ref_var, torch.float32), _ptr(ref_mask, torch.uint8), _ptr(sci, torch.float32),
             _ptr(sci_var, torch.float32), _ptr(sci_mask, torch.uint8),
-            _ptr(coeffs, torch.float64), _ptr(n_fit, torch.int64), _ptr(status, torch.int32)))
+            _ptr(coeffs, torch.float64), _ptr(chi2, torch.float64), _ptr(n_fit, torch.int64),
+            _ptr(status, torch.int32)))
 
     def expand_kernel(self, spec, coeffs, stamps, bg):
         torch = self._torch

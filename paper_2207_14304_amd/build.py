@@ -1,6 +1,6 @@
 """Build libargus.so (HIP, gfx950) in-tree.
 
-Usage: python -m paper_2207_14304_amd.build
+Usage: python -m paper_2207_14304_amd.build [--incremental]
 """
 from __future__ import annotations
 
@@ -35,10 +35,24 @@ def _compile(src):
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src):
+    """True when the object of src is older than src or any header."""
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "argus.h"))
+    return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, incremental, only stale objects) and link."""
     os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    todo = [s for s in srcs if _stale(s)] if incremental else srcs
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, sources()))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     tmp = OUT + ".tmp"
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                        capture_output=True, text=True)
@@ -51,5 +65,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

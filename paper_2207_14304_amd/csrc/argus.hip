@@ -106,6 +106,7 @@ void argus_ctx_destroy(argus_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->tables) (void)hipFree(ctx->tables);
+    if (ctx->fit_stamps) (void)hipFree(ctx->fit_stamps);
     release_times(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -248,7 +249,7 @@ int argus_kernel_dims(const argus_kernel_spec *spec, int *n_unknowns, int *n_sol
 int argus_fit_kernel(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
                      const float *ref, const float *ref_var, const uint8_t *ref_mask,
                      const float *sci, const float *sci_var, const uint8_t *sci_mask,
-                     double *coeffs, int64_t *n_fit, int32_t *status) {
+                     double *coeffs, double *chi2, int64_t *n_fit, int32_t *status) {
     if (!ctx) return ARGUS_EINVAL;
     ctx->err.clear();
     int rc = check_dims(ctx, dims);
@@ -258,9 +259,41 @@ int argus_fit_kernel(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *s
         return argus_fail(ctx, ARGUS_EINVAL, "argus_fit_kernel: null pointer");
     if (spec->tiles_x > dims.width || spec->tiles_y > dims.height)
         return argus_fail(ctx, ARGUS_ESHAPE, "more tiles than pixels");
+    float *stamps = nullptr, *bg = nullptr;
+    if (chi2) {
+        // the stamp buffer for the residual pass, reserved before any launch
+        int n, ns;
+        (void)argus_kernel_dims(spec, &n, &ns);
+        const int K = 2 * spec->half_width + 1;
+        const size_t n_st = (size_t)ns * argus_npoly(spec->spatial_degree) * K * K;
+        const size_t n_bg = (size_t)ns * argus_npoly(spec->bg_degree);
+        const size_t bytes = ((n_st * 4 + 255) & ~(size_t)255) + n_bg * 4;
+        if (bytes > ctx->fit_stamps_bytes) {
+            if (stream_capturing(ctx))
+                return argus_fail(ctx, ARGUS_EBUSY, "chi2 stamp buffer needed during stream capture");
+            if (ctx->fit_stamps) {
+                ARGUS_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+                ARGUS_HIP_CHECK(ctx, hipFree(ctx->fit_stamps));
+                ctx->fit_stamps = nullptr;
+                ctx->fit_stamps_bytes = 0;
+            }
+            if (hipMalloc(&ctx->fit_stamps, bytes) != hipSuccess) {
+                ctx->fit_stamps = nullptr;
+                return argus_fail(ctx, ARGUS_ENOMEM, "chi2 stamp buffer of %zu bytes", bytes);
+            }
+            ctx->fit_stamps_bytes = bytes;
+        }
+        stamps = (float *)ctx->fit_stamps;
+        bg = (float *)((char *)ctx->fit_stamps + ((n_st * 4 + 255) & ~(size_t)255));
+    }
     if ((rc = launch_basis_tables(ctx, spec))) return rc;
-    return launch_fit(ctx, dims, spec, ref, ref_var, ref_mask, sci, sci_var, sci_mask, coeffs,
-                      n_fit, status);
+    rc = launch_fit(ctx, dims, spec, ref, ref_var, ref_mask, sci, sci_var, sci_mask, coeffs,
+                    n_fit, status);
+    if (rc || !chi2) return rc;
+    // second pass over the residuals: D = S - X a at every fit pixel
+    if ((rc = launch_expand(ctx, spec, coeffs, stamps, bg))) return rc;
+    return launch_subtract(ctx, dims, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var,
+                           sci_mask, nullptr, nullptr, nullptr, chi2, nullptr, nullptr, nullptr);
 }
 
 int argus_expand_kernel(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,

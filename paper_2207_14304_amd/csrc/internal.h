@@ -44,6 +44,9 @@ struct argus_ctx {
     BasisTables *tables = nullptr;
     bool tables_valid = false;
     argus_kernel_spec tables_spec{};
+    // stamps and background of the fit's chi^2 pass (grown on first use)
+    void *fit_stamps = nullptr;
+    size_t fit_stamps_bytes = 0;
     // optional per-kernel timing: an event pair per timed launch, read back
     // (and averaged per kernel name) only when queried
     bool timing = false;
@@ -99,6 +102,8 @@ int launch_coadd(argus_ctx *ctx, argus_dims d, int n, const float *const *cal,
                  int max_iter, float *ref, float *ref_var, uint8_t *ref_mask,
                  uint8_t *n_used);
 int launch_basis_tables(argus_ctx *ctx, const argus_kernel_spec *spec);
+// fill dst (any BasisTables buffer) for spec on the context stream
+int launch_basis_tables_to(argus_ctx *ctx, const argus_kernel_spec *spec, BasisTables *dst);
 int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                const float *ref, const float *ref_var, const uint8_t *ref_mask,
                const float *sci, const float *sci_var, const uint8_t *sci_mask,

@@ -26,7 +26,9 @@ struct argus_batch {
     int n = 0, n_frames = 0, n_unk = 0, h = 0, nb = 0, nplanes = 0;
     argus_kernel_spec spec{};
     int8_t plist[4][4];
-    void *dev = nullptr;            // device: cutouts, order, frames, queue
+    void *dev = nullptr;            // device: cutouts, order, frames, queue, basis tables
+    BasisTables *d_tables = nullptr;  // the batch's own copy: the context's tables
+                                      // change with every other spec used on it
     argus_cutout *d_cuts = nullptr;
     int32_t *d_order = nullptr;
     argus_frame *d_frames = nullptr;
@@ -482,7 +484,6 @@ int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec, const argus_
             return argus_fail(ctx, ARGUS_ESHAPE, "cutout %d leaves its frame", i);
         if (c.out_offset < 0) return argus_fail(ctx, ARGUS_EINVAL, "cutout %d: negative offset", i);
     }
-    if ((rc = launch_basis_tables(ctx, spec))) return rc;
     argus_batch *b = new argus_batch();
     b->n = n_cutouts;
     b->n_frames = n_frames;
@@ -522,8 +523,8 @@ int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec, const argus_
     size_t bc = (size_t)n_cutouts * sizeof(argus_cutout), bo = (size_t)n_cutouts * 4,
            bf = (size_t)n_frames * sizeof(argus_frame);
     size_t off_o = (bc + 255) & ~(size_t)255, off_f = (off_o + bo + 255) & ~(size_t)255,
-           off_q = (off_f + bf + 255) & ~(size_t)255;
-    if (hipMalloc(&b->dev, off_q + 256) != hipSuccess) {
+           off_q = (off_f + bf + 255) & ~(size_t)255, off_t = off_q + 256;
+    if (hipMalloc(&b->dev, off_t + sizeof(BasisTables)) != hipSuccess) {
         delete b;
         return argus_fail(ctx, ARGUS_ENOMEM, "batch tables");
     }
@@ -531,6 +532,7 @@ int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec, const argus_
     b->d_order = (int32_t *)((char *)b->dev + off_o);
     b->d_frames = (argus_frame *)((char *)b->dev + off_f);
     b->d_queue = (int32_t *)((char *)b->dev + off_q);
+    b->d_tables = (BasisTables *)((char *)b->dev + off_t);
     if (hipMemcpy(b->d_cuts, cutouts, bc, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_order, order.data(), bo, hipMemcpyHostToDevice) != hipSuccess ||
         hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
@@ -538,6 +540,10 @@ int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec, const argus_
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
         argus_batch_destroy(b);
         return argus_fail(ctx, ARGUS_EHIP, "batch setup failed");
+    }
+    if ((rc = launch_basis_tables_to(ctx, spec, b->d_tables))) {
+        argus_batch_destroy(b);
+        return rc;
     }
     // the basis tables must be complete before the private stream reads them
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -578,7 +584,7 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *b, const argus_frame *frames, f
         ARGUS_HIP_CHECK(ctx, hipStreamSynchronize(b->stream));
         BatchArgs ba;
         ba.frames = b->d_frames; ba.cuts = b->d_cuts; ba.order = b->d_order; ba.queue = b->d_queue;
-        ba.tab = ctx->tables; ba.n = b->n; ba.nb = b->nb; ba.nplanes = b->nplanes; ba.n_unk = b->n_unk;
+        ba.tab = b->d_tables; ba.n = b->n; ba.nb = b->nb; ba.nplanes = b->nplanes; ba.n_unk = b->n_unk;
         memcpy(ba.plist, b->plist, sizeof ba.plist);
         ba.thr = threshold;
         ba.diff = diff; ba.dvar = diff_var; ba.dmask = diff_mask; ba.det = det_mask;

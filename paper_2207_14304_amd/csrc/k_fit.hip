@@ -402,6 +402,12 @@ int fit_launch_d(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, Fi
 
 }  // namespace
 
+int launch_basis_tables_to(argus_ctx *ctx, const argus_kernel_spec *spec, BasisTables *dst) {
+    hipLaunchKernelGGL(basis_tables_kernel, dim3(1), dim3(256), 0, ctx->stream, *spec, dst);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    return ARGUS_OK;
+}
+
 int launch_basis_tables(argus_ctx *ctx, const argus_kernel_spec *spec) {
     const argus_kernel_spec &o = ctx->tables_spec;
     bool same = ctx->tables_valid && o.n_gauss == spec->n_gauss && o.half_width == spec->half_width;

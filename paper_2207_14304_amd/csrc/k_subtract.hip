@@ -27,6 +27,7 @@ struct SubArgs {
     int RX, RY, bpx, bpy;      // regions and blocks per region
     double sx, sy;
     int vec;
+    int write;                 // 0: only the sums (diff, dvar, dmask are null)
 };
 
 template <int HH>
@@ -264,7 +265,9 @@ __global__ __launch_bounds__(NTHR) void subtract_kernel(SubArgs a) {
             }
             const int X0 = bx0 + lx0;
             const int64_t o0 = orow + X0;
-            if (a.vec && (X0 & 7) == 0 && X0 + PXT <= bx1) {
+            if (!a.write) {
+                // chi^2 pass of the fit: no images written
+            } else if (a.vec && (X0 & 7) == 0 && X0 + PXT <= bx1) {
                 *(float4 *)(a.diff + o0) = make_float4(outd[0], outd[1], outd[2], outd[3]);
                 *(float4 *)(a.diff + o0 + 4) = make_float4(outd[4], outd[5], outd[6], outd[7]);
                 *(float4 *)(a.dvar + o0) = make_float4(outv[0], outv[1], outv[2], outv[3]);
@@ -384,6 +387,7 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
     a.sx = d.width > 1 ? 2.0 / (d.width - 1) : 0.0;
     a.sy = d.height > 1 ? 2.0 / (d.height - 1) : 0.0;
     a.vec = (d.pitch % 8 == 0) && aligned(diff, 32) && aligned(diff_var, 32) && aligned(diff_mask, 8);
+    a.write = diff != nullptr;
     const int n_solves = a.RX * a.RY;
     const int per_solve = a.bpx * a.bpy;
     const int n_blocks = n_solves * per_solve;

@@ -59,7 +59,7 @@ def _spec(precision=argus.FP64):
     return argus.make_spec(half_width=H_K, precision=precision)
 
 
-def _run(ctx, frames, cut, reps=1, precision=argus.FP64):
+def _run(ctx, frames, cut, reps=1, precision=argus.FP64, between=None):
     import torch
     fr, x0, y0, L = cut
     spec = _spec(precision)
@@ -73,7 +73,9 @@ def _run(ctx, frames, cut, reps=1, precision=argus.FP64):
                 n_fit=empty(n, torch.int64), status=empty(n, torch.int32),
                 n_cands=empty(n, torch.int32))
     results = []
-    for _ in range(reps):
+    for rep in range(reps):
+        if between is not None:
+            between(rep)
         ctx.batch_run(b, dframes, 5.0, outs["diff"], outs["var"], outs["mask"], outs["det"],
                       outs["coeffs"], outs["chi2"], outs["n_fit"], outs["status"],
                       outs["n_cands"])
@@ -176,3 +178,47 @@ def test_batch_rejects_bad_cutouts(ctx, frames):
     with pytest.raises(argus.ArgusError):
         argus.Batch(ctx, argus.make_spec(half_width=7, spatial_degree=1), [0], [0], [0], [64],
                     [fp.W], [fp.H])
+
+
+def test_batch_keeps_its_basis_across_other_fits(ctx, frames):
+    """The captured graph reads the basis tables of the batch's own plan.
+    Fits and kernel expansions with other specs on the same context (21x21
+    degree-2 and 11x11 constant kernels rebuild the context's tables) between
+    the plan and the first run and between graph replays change none of the
+    batch's outputs, which still match the oracle."""
+    import torch
+    cut = _cutouts(frames, 6, 300)
+    _, (clean,) = _run(ctx, frames, cut)
+    dplanes = [dev(p) for p in frames[0]["host"]]
+    specs = [argus.make_spec(half_width=10, spatial_degree=2, bg_degree=2),
+             argus.make_spec(half_width=5)]
+
+    def other_fit(rep):
+        spec = specs[rep % 2]
+        n, ns = argus.kernel_dims(spec)
+        co = empty((ns, n), torch.float64)
+        ctx.fit_kernel(spec, *dplanes, co, empty(ns, torch.int64), empty(ns, torch.int32))
+        nP = 6 if rep % 2 == 0 else 1
+        K = 2 * spec.half_width + 1
+        ctx.expand_kernel(spec, co, empty((ns, nP, K, K), torch.float32),
+                          empty((ns, nP), torch.float32))
+
+    b, res = _run(ctx, frames, cut, reps=3, between=other_fit)
+    for r in res:
+        for k in clean:
+            if k == "chi2":       # its sum order follows the autotuned tile height
+                assert np.allclose(r[k], clean[k], rtol=1e-12, atol=0), k
+            else:
+                assert np.array_equal(r[k], clean[k]), k
+    fr, x0, y0, L = cut
+    ospec = oracle.KernelSpec(half_width=H_K)
+    B = oracle.basis(ospec)
+    for i in (0, b.n - 1):
+        o = _oracle_cutout(frames, fr[i], x0[i], y0[i], L[i])
+        gst = np.tensordot(res[-1]["coeffs"][i][:31], B, 1)
+        assert np.abs(gst - o["stamps"]).max() <= STAMP_TOL[argus.FP64] * np.abs(o["stamps"]).max()
+        off, n2 = b.offsets[i], L[i] * L[i]
+        gD = res[-1]["diff"][off:off + n2].reshape(L[i], L[i])
+        ok = o["dm"] == 0
+        err = (gD[ok] - o["D"][ok]) / np.sqrt(o["V"][ok])
+        assert np.sqrt(np.mean(err ** 2)) <= RMS_TOL[argus.FP64]

@@ -65,7 +65,7 @@ def test_largest_kernel_fit_and_subtraction(ctx, prec):
     planes = _noisy_pair(240, 210, 151, n_stars=220)
     spec = _spec(half_width=h, spatial_degree=1, bg_degree=1, precision=prec)
     os_ = _ospec(spec)
-    co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+    co, nf, st, stamps, bg, _ = _fit(ctx, spec, planes)
     oco, ost, onf = oracle.fit_kernel(*planes, os_)
     assert st[0] == 0 and ost[0] == 0 and nf[0] == onf[0]
     o_stamps, o_bg = oracle.expand_kernel(oco, os_)

@@ -267,14 +267,16 @@ def _fit(ctx, spec, planes):
     co = empty((ns, n), torch.float64)
     nf = empty(ns, torch.int64)
     st = empty(ns, torch.int32)
-    ctx.fit_kernel(spec, dev(cr), dev(vr), dev(mr), dev(cs), dev(vs), dev(ms), co, nf, st)
+    c2 = empty(ns, torch.float64)
+    ctx.fit_kernel(spec, dev(cr), dev(vr), dev(mr), dev(cs), dev(vs), dev(ms), co, nf, st,
+                   chi2=c2)
     nP = (spec.spatial_degree + 1) * (spec.spatial_degree + 2) // 2
     nPb = (spec.bg_degree + 1) * (spec.bg_degree + 2) // 2
     K = 2 * spec.half_width + 1
     stamps = empty((ns, nP, K, K), torch.float32)
     bg = empty((ns, nPb), torch.float32)
     ctx.expand_kernel(spec, co, stamps, bg)
-    return host(co), host(nf), host(st), host(stamps), host(bg)
+    return host(co), host(nf), host(st), host(stamps), host(bg), host(c2)
 
 
 @pytest.mark.parametrize("prec", [argus.FP32, argus.FP64])
@@ -302,7 +304,7 @@ def test_fit_exact_recovery(ctx, D, mode, tiles, prec):
     ones = np.ones((H, W), np.float32)
     z = np.zeros((H, W), np.uint8)
     planes = (ref.astype(np.float32), ones, z, S.astype(np.float32), ones, z)
-    co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+    co, nf, st, stamps, bg, fc2 = _fit(ctx, spec, planes)
     assert np.all(st == 0)
     o_stamps, o_bg = oracle.expand_kernel(np.array(a_true), os_)
     err = np.abs(stamps - o_stamps).max() / np.abs(o_stamps).max()
@@ -324,7 +326,7 @@ def test_fit_parity_noisy(ctx, D, h, tiles, prec):
     spec = _spec(half_width=h, spatial_degree=D, bg_degree=D, tiles_x=tiles[0], tiles_y=tiles[1],
                  precision=prec)
     os_ = _ospec(spec)
-    co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+    co, nf, st, stamps, bg, fc2 = _fit(ctx, spec, planes)
     oco, ost, onf = oracle.fit_kernel(*planes, os_)
     assert st[0] == 0 and ost[0] == 0
     assert nf[0] == onf[0]
@@ -332,9 +334,13 @@ def test_fit_parity_noisy(ctx, D, h, tiles, prec):
     err = np.abs(stamps - o_stamps).max() / np.abs(o_stamps).max()
     gc2 = oracle.chi2(*planes, os_, co)
     oc2 = oracle.chi2(*planes, os_, oco)
-    print(f"prec {prec} D {D} h {h}: stamp error {err:.3e}, chi2 ratio - 1 {gc2[0] / oc2[0] - 1:.3e}")
+    print(f"prec {prec} D {D} h {h}: stamp error {err:.3e}, chi2 ratio - 1 {gc2[0] / oc2[0] - 1:.3e}"
+          f", fit chi2 pass vs oracle {fc2[0] / gc2[0] - 1:.3e}")
     assert err <= NOISY_STAMP_TOL[prec]
     assert abs(gc2[0] / oc2[0] - 1) <= NOISY_CHI2_TOL[prec]
+    # the fit's own chi^2 (second pass over the residuals) against the
+    # oracle's at the GPU's coefficients: the chi^2 bar
+    assert abs(fc2[0] / gc2[0] - 1) <= 1e-5
 
 
 def _jacobi_cond(planes, os_):
@@ -362,7 +368,7 @@ def test_fit_parity_basis_layouts(ctx, sigmas, degrees, prec):
     spec = argus.make_spec(sigmas=sigmas, degrees=degrees, half_width=7, spatial_degree=1,
                            bg_degree=1, precision=prec)
     os_ = _ospec(spec)
-    co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+    co, nf, st, stamps, bg, fc2 = _fit(ctx, spec, planes)
     oco, ost, onf = oracle.fit_kernel(*planes, os_)
     assert st[0] == ost[0] == 0
     assert nf[0] == onf[0]
@@ -382,7 +388,7 @@ def test_fit_per_tile_parity(ctx):
     planes = _noisy_pair(290, 260, 77, n_stars=400)
     spec = _spec(half_width=7, tiles_x=2, tiles_y=2, mode=argus.FIT_PER_TILE)
     os_ = _ospec(spec)
-    co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+    co, nf, st, stamps, bg, fc2 = _fit(ctx, spec, planes)
     oco, ost, onf = oracle.fit_kernel(*planes, os_)
     assert np.array_equal(st, ost) and np.array_equal(nf, onf)
     o_stamps, _ = oracle.expand_kernel(oco, os_)
@@ -398,12 +404,13 @@ def test_fit_status_codes(ctx):
     spec = _spec(half_width=5, tiles_x=2, tiles_y=1, mode=argus.FIT_PER_TILE)
     sm = z.copy()
     sm[:, : W // 2] = oracle.BAD                    # left tile fully masked
-    co, nf, st, _, _ = _fit(ctx, spec, (ref, ones, z, ref, ones, sm))
+    co, nf, st, _, _, fc2 = _fit(ctx, spec, (ref, ones, z, ref, ones, sm))
     assert st[0] == argus.ETOOFEW and nf[0] == 0 and np.all(np.isnan(co[0]))
+    assert np.isnan(fc2[0]) and np.isfinite(fc2[1])
     assert st[1] == argus.OK
     flat_ref = np.full((H, W), 100.0, np.float32)  # every basis image is constant
-    co, nf, st, _, _ = _fit(ctx, _spec(half_width=5), (flat_ref, ones, z, flat_ref, ones, z))
-    assert st[0] == argus.ESINGULAR and np.all(np.isnan(co[0]))
+    co, nf, st, _, _, fc2 = _fit(ctx, _spec(half_width=5), (flat_ref, ones, z, flat_ref, ones, z))
+    assert st[0] == argus.ESINGULAR and np.all(np.isnan(co[0])) and np.isnan(fc2[0])
 
 
 def test_fit_is_deterministic(ctx):
@@ -424,7 +431,7 @@ def test_fit_subtract_chain_parity(ctx, prec):
         spec = _spec(half_width=h, spatial_degree=D, bg_degree=D, tiles_x=tiles[0],
                      tiles_y=tiles[1], precision=prec)
         os_ = _ospec(spec)
-        co, nf, st, stamps, bg = _fit(ctx, spec, planes)
+        co, nf, st, stamps, bg, fc2 = _fit(ctx, spec, planes)
         g = _run_subtract(ctx, spec, stamps, bg, planes)
         oco, ost, onf = oracle.fit_kernel(*planes, os_)
         ost_, obg = oracle.expand_kernel(oco, os_)
@@ -432,6 +439,9 @@ def test_fit_subtract_chain_parity(ctx, prec):
         gD, gV, gM = g[0], g[1], g[2]
         oD, oV, oM = o[0], o[1], o[2]
         assert np.array_equal(gM, oM)
+        # the fit's chi^2 pass is the subtraction on the same stamps: same sums
+        assert np.array_equal(fc2, g[3])
+        assert abs(fc2[0] / o[3][0] - 1) <= 1e-5
         ok = oM == 0
         err = (gD[ok] - oD[ok]) / np.sqrt(oV[ok])
         rms, mx = np.sqrt(np.mean(err ** 2)), np.abs(err).max()

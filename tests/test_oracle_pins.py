@@ -104,6 +104,18 @@ def test_coadd_even_median_and_survivor_floor():
     assert nu[0, 0] == 2 and ref[0, 0] == 100.0 and rv[0, 0] == 0.5
 
 
+def test_coadd_margin_marks_exact_ties():
+    cal = [np.array([[1000.0, 1000.0]]), np.array([[1000.0, 1000.0]]),
+           np.array([[1000.0, 1000.0]]), np.array([[1000.0, 1000.0]]),
+           np.array([[1030.0, 1015.0]])]
+    var = [np.full((1, 2), 100.0)] * 5
+    msk = [np.zeros((1, 2), np.uint8)] * 5
+    ref, rv, rm, nu, mg = oracle.coadd(cal, var, msk, 3.0, 5, return_margin=True)
+    # |1030 - 1000| = 3 sigma exactly: kept (strict >), margin 0;
+    # 1015 is 1.5 sigma out, 1000s are 3 sigma in: margin 0.5
+    assert nu.tolist() == [[5, 5]] and mg[0, 0] == 0.0 and mg[0, 1] == pytest.approx(0.5)
+
+
 def test_coadd_nodata_and_sat():
     ref, rv, rm, nu = _stack([1.0] * 5, None, [oracle.BAD] * 5)
     assert nu[0, 0] == 0 and ref[0, 0] == 0 and rm[0, 0] == oracle.NODATA
