@@ -17,9 +17,10 @@ Bars: the reference's n_used and mask bit-exact except at pixels where the
 oracle's clip decision is within 1e-5 of its threshold (counted); the
 difference mask bit-exact; the difference image RMS of (D_gpu - D_oracle)/sigma
 <= 1e-4 and max <= 1e-2 over pixels whose footprint holds no such coadd
-near-tie; V relative <= 1e-5; chi^2/dof relative <= 1e-5; the candidates
-equal except where the oracle's SNR is within 1e-3 of the threshold
-(counted), their fluxes relative <= 1e-4.
+near-tie; V relative <= 1e-5; chi^2/dof relative <= 1e-5; the SNR map
+within the difference image's bars (it is D/sigma); the candidates equal
+except where the oracle's SNR is within 1e-3 of the threshold or of an
+8-neighbour's (counted), their fluxes relative <= 1e-4.
 """
 import numpy as np
 import pytest
@@ -112,11 +113,31 @@ def test_chi2(chain):
     assert g["fit_chi2"][0] == g["chi2"][0]      # the fit's own residual pass
 
 
+def _near_ties(snr, thr, tol):
+    """Pixels whose threshold or local-maximum decision lies within tol of
+    the oracle's: |snr - thr| <= tol, or above threshold with an 8-neighbour
+    within tol of its SNR."""
+    H, W = snr.shape
+    near = np.abs(snr - thr) <= tol
+    pad = np.full((H + 2, W + 2), -np.inf)
+    pad[1:-1, 1:-1] = snr
+    close = np.zeros_like(near)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dx or dy:
+                close |= np.abs(snr - pad[1 + dy:H + 1 + dy, 1 + dx:W + 1 + dx]) <= tol
+    return near | (close & (snr >= thr - tol))
+
+
 def test_detection(chain):
     g, o = chain
-    near = np.abs(o["snr"] - 5.0) <= 1e-3
+    near = _near_ties(o["snr"], 5.0, 1e-3)
     ok = (o["M"] == 0)
-    assert np.abs(g["snr"][ok] - o["snr"][ok]).max() <= 1e-4
+    # chained, SNR = D / sigma carries the difference image's error in sigma
+    # units, so its bars are the difference image's (RMS 1e-4, max 1e-2)
+    e = g["snr"][ok] - o["snr"][ok]
+    print(f"SNR error: RMS {np.sqrt(np.mean(e ** 2)):.3e}, max {np.abs(e).max():.3e}")
+    assert np.sqrt(np.mean(e ** 2)) <= 1e-4 and np.abs(e).max() <= 1e-2
     assert np.array_equal(g["det"][~near], o["det"][~near])
     gc, oc = g["cands"], o["cands"]
     gkeys = set(zip(gc["x"].tolist(), gc["y"].tolist()))
