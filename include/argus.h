@@ -103,6 +103,22 @@ typedef struct {
     float snr, flux, flux_err;
 } argus_candidate;
 
+/* gnomonic (TAN) world coordinates of a frame: pixel (x, y) has standard
+ * coordinates (xi, eta) = cd * (x - crpix1, y - crpix2) in degrees, cd
+ * row-major {cd11, cd12, cd21, cd22}, about the direction (ra0, dec0) in
+ * degrees (Calabretta & Greisen 2002). */
+typedef struct {
+    double ra0, dec0;
+    double crpix1, crpix2;
+    double cd[4];
+} argus_wcs;
+
+/* a source of argus_detect_sources: peak pixel, centroid, peak SNR, PSF flux */
+typedef struct {
+    int32_t x, y;
+    float xc, yc, snr, flux, flux_err;
+} argus_source;
+
 /* ---- context ------------------------------------------------------------ */
 /* Create a context on HIP device `device`; work goes to the null stream until
  * argus_ctx_set_stream.  One context per host thread. */
@@ -116,7 +132,9 @@ const char *argus_last_error(const argus_ctx *ctx);
  * an internal kernel is bracketed by HIP events on the context stream, with
  * no synchronisation.  argus_kernel_time_ms waits for the recorded launches
  * of the named kernel ("calibrate", "coadd", "calibrate_coadd", "fit_accum",
- * "fit_reduce", "fit_solve", "subtract", "detect_map", "batch") and returns
+ * "fit_reduce", "fit_solve", "subtract", "detect_map", "detect_emit",
+ * "background", "background_map", "source_map", "source_emit", "coadd_matched",
+ * "healpix_resample", "zogy", "batch") and returns
  * their average device time in ms, or -1 if none was recorded.  Enabling or
  * disabling timing discards the records. */
 int  argus_ctx_set_timing(argus_ctx *ctx, int enable);
@@ -238,6 +256,125 @@ int argus_detect(argus_ctx *ctx, argus_dims dims,
                  float threshold, const float *psf, int psf_half,
                  float *snr, uint8_t *det_mask,
                  argus_candidate *cands, int32_t capacity, int32_t *n_cands);
+
+/* ---- background map (Pipeline Implementation: calibration and source
+ * detection on the GPU; Compute Nodes: background and noise maps kept with
+ * the calibration frames; Table 2, "median-filtered background map") -------
+ * The frame is cut into box x box cells from the origin (box 4..64; the last
+ * cell of a row or column spans the remainder).  levels[c] (f32 [gy][gx],
+ * gx = ceil(W/box), gy = ceil(H/box), nullable) = the exact median of the
+ * cell's calibrated values with mask == 0 (an even count: the mean of the
+ * middle pair, rounded once to FP32), NaN where the cell has none.
+ * grid[c] (f32 [gy][gx]) = the median of the levels present in the cell's
+ * 3 x 3 neighbourhood of cells (0 if none).  map (f32 [H][W] with the dims'
+ * pitch, nullable) = the bilinear interpolation of grid between cell centres
+ * ((x0 + x1 - 1)/2 of a cell spanning [x0, x1)), held constant beyond the
+ * outer centres.  cal f32 and mask u8 as written by argus_calibrate.
+ * Errors: ARGUS_EINVAL for null inputs or grid, ARGUS_ESHAPE for box outside
+ * 4..64.  With levels null the ctx workspace holds them. */
+int argus_background(argus_ctx *ctx, argus_dims dims, const float *cal, const uint8_t *mask,
+                     int box, float *levels, float *grid, float *map);
+
+/* ---- full-frame source detection (Pipeline Implementation; Table 2,
+ * "source detection") ------------------------------------------------------
+ * argus_detect on D = cal - background (grid of argus_background with the
+ * same box, evaluated per pixel as its map), V = var and mask = the
+ * calibration mask: snr (nullable), det_mask (DET, CAND), and per source, in
+ * raster order, the peak pixel, its SNR, the PSF-weighted flux and error, and
+ * the centroid (xc, yc) = (x, y) + sum (u, v) max(D, 0) / sum max(D, 0) over
+ * the unmasked in-image 3 x 3 neighbourhood (NaN if that sum is 0).
+ * sources (device, capacity entries); *n_sources (device i32) receives the
+ * true count.  Errors as for argus_detect and argus_background. */
+int argus_detect_sources(argus_ctx *ctx, argus_dims dims, const float *cal, const float *var,
+                         const uint8_t *mask, const float *grid, int box, float threshold,
+                         const float *psf, int psf_half, float *snr, uint8_t *det_mask,
+                         argus_source *sources, int32_t capacity, int32_t *n_sources);
+
+/* ---- matched-filter coadd (Deep Coaddition in Sky Segments: a per-image
+ * matched filter, the optimal coaddition for point-source detection in
+ * background-limited images of Zackay & Ofek 2017) -------------------------
+ * For n_frames (1..8) registered images j with variance var_j, mask_j and an
+ * optional background grid grid_j (argus_background with the given box;
+ * grids or any entry may be null: no background), PSF P_j (psf: device f32
+ * [n_frames][2r+1][2r+1], r = psf_half 1..10, unit sum, P[dv+r][du+r] for the
+ * offset (du, dv)) and flux zero point F_j (scales: HOST f32 [n_frames], null
+ * = all 1), per pixel q with M_j = cal_j - background_j:
+ *   score(q)     = sum_j F_j   sum_u P_j(u)   M_j(q+u) / var_j(q+u)
+ *   score_var(q) = sum_j F_j^2 sum_u P_j(u)^2 / var_j(q+u)
+ * over in-image pixels q+u with mask_j == 0 and var_j > 0; snr (nullable) =
+ * score / sqrt(score_var), 0 where score_var == 0.  score_var is the
+ * variance of score for independent pixel noise; score / score_var is the
+ * PSF flux of a point source at q (in units of F = 1) and score_var^-1/2 its
+ * error.  cal/var/mask/grids are HOST arrays of DEVICE pointers; outputs f32
+ * with the dims' pitch.  FP32 products, summed in FP32 along a PSF row and in
+ * FP64 across rows and images.  Errors: ARGUS_EINVAL (null pointers,
+ * n_frames), ARGUS_ESHAPE (psf_half, box). */
+int argus_coadd_matched(argus_ctx *ctx, argus_dims dims, int n_frames,
+                        const float *const *cal, const float *const *var,
+                        const uint8_t *const *mask, const float *const *grids, int box,
+                        const float *psf, int psf_half, const float *scales,
+                        float *score, float *score_var, float *snr);
+
+/* ---- HEALPix segments (Image Segmentation: every frame reprojected into
+ * equal-area NSIDE = 256 sky tiles on the GPU; Table 2, "image segmentation
+ * and resampling to HEALPix grid") -----------------------------------------
+ * Geometry: the HEALPix projection (Gorski et al. 2005) maps the sphere to
+ * a plane where the 12 base pixels are diamonds; face coordinates (a, b) in
+ * [0, 1]^2 run from a diamond's south corner to its east (a) and west (b)
+ * corners; base pixel f is centred at (pi/4 + f pi/2, pi/4) for f = 0..3,
+ * ((f-4) pi/2, 0) for 4..7 and (pi/4 + (f-8) pi/2, -pi/4) for 8..11.  Tile
+ * (f, I, J) of NSIDE nside covers a in [I, I+1)/nside, b in [J, J+1)/nside.
+ *
+ * argus_healpix_tiles (host only): the tiles (f, I, J) that the frame's
+ * pixels fall in, sampled every `step` pixels along x and y and along the
+ * last row and column, sorted (f, I, J) ascending, into the HOST array tiles
+ * [capacity][3]; *n_tiles (host) receives the true count.  ARGUS_EINVAL for
+ * null pointers, a singular cd or non-positive sizes.
+ *
+ * argus_resample_healpix: for each of n_tiles tiles (DEVICE i32 [n][3]) an
+ * m x m segment image whose pixel (p, q) (row q) is the HEALPix pixel of
+ * NSIDE nside*m at a = (I m + p + 1/2)/(nside m), b = (J m + q + 1/2)/(nside m):
+ * the frame is bilinearly interpolated at that direction's frame position
+ * (wcs): out = sum w cal, out_var = sum w^2 var over the four neighbours
+ * (FP64 weights), out_mask 0; NODATA (out = out_var = 0) where the position
+ * is off [0, W-1] x [0, H-1], behind the tangent plane, or a neighbour is
+ * masked.  Outputs f32/f32/u8 [n_tiles][m][m].  nside 1..2^20, m 1..4096.
+ * FP64 geometry.  Errors: ARGUS_EINVAL (null pointers, singular cd),
+ * ARGUS_ESHAPE (sizes). */
+int argus_healpix_tiles(const argus_wcs *wcs, int width, int height, int nside, int step,
+                        int32_t *tiles, int capacity, int *n_tiles);
+int argus_resample_healpix(argus_ctx *ctx, argus_dims dims, const float *cal, const float *var,
+                           const uint8_t *mask, const argus_wcs *wcs, int nside, int m,
+                           const int32_t *tiles, int n_tiles, float *out, float *out_var,
+                           uint8_t *out_mask);
+
+/* ---- ZOGY subtraction (Transient Alerts: the algorithm of Zackay, Ofek &
+ * Gal-Yam 2016 for the 30-second cadence and deep coadds; Table 2, "ZOGY
+ * image subtraction") -------------------------------------------------------
+ * On n_tiles square tiles of side L (a power of two, 64..1024) at origins
+ * (DEVICE i32 [n][2]: x0, y0; tiles may overlap or leave the frame) of the
+ * background-subtracted new image N and reference R (f32 with masks u8; a
+ * masked or off-frame pixel enters both as 0), with unit-sum PSF stamps psf_n,
+ * psf_r (DEVICE f32 [2r+1]^2, r = psf_half 1..15, 4r + 2 <= L), flux zero
+ * points Fn, Fr > 0 and background noise sigmas sn, sr >= 0 (not both 0),
+ * in the Fourier domain of the periodic tile:
+ *   den = sqrt(sn^2 Fr^2 |Pr^|^2 + sr^2 Fn^2 |Pn^|^2),
+ *   D^ = (Fr Pr^ N^ - Fn Pn^ R^)/den  (0 where den = 0),
+ *   F_D = Fn Fr / sqrt(sn^2 Fr^2 + sr^2 Fn^2),  P_D^ = Fr Fn Pr^ Pn^/(F_D den),
+ *   S^ = D^ conj(P_D^);
+ * outputs per tile pixel (f32/u8 [n][L][L]): D (white, unit variance for
+ * white input noise of the given sigmas), snr = S/sqrt(sum P_D^2), flux =
+ * S/(F_D sum P_D^2) (the flux of a point source there), mask = EDGE within r
+ * of the tile border | FOOT within 2r (Chebyshev) of a masked or off-frame
+ * pixel, with D = snr = flux = 0 where flagged.  sum P_D^2 is written to
+ * pd2 (DEVICE f64, nullable).  FP64 transforms and arithmetic; workspace
+ * grows to about 70 n L^2 bytes.  Errors: ARGUS_EINVAL (null pointers,
+ * scalars), ARGUS_ESHAPE (L, r, n). */
+int argus_zogy(argus_ctx *ctx, argus_dims dims, const float *new_img, const uint8_t *new_mask,
+               const float *ref, const uint8_t *ref_mask, const int32_t *origins, int n_tiles,
+               int L, const float *psf_n, const float *psf_r, int psf_half, double Fn, double Fr,
+               double sn, double sr, float *D, float *snr, float *flux, uint8_t *mask,
+               double *pd2);
 
 /* ---- batched cutouts (per-segment subtraction, Transient Alerts; Table 2) --
  * Many target cutouts from many cameras' frames, each fit with its own

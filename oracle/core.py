@@ -278,16 +278,19 @@ def design_rows(C, xt, yt, ys, xs, spec):
     return X
 
 
-def normal_equations(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B=None, C=None):
+def normal_equations(ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, B=None, C=None,
+                     coords=None):
     """Per tile t: A_t = sum w X X^T, b_t = sum w X S over the fit set in t,
     with w = 1/(var_S + var_R).  Returns (A [T][n][n], b [T][n], n_fit [T])
-    for the tiles in raster order.  C, if given, is convolve(ref, B)."""
+    for the tiles in raster order.  C, if given, is convolve(ref, B); coords,
+    if given, are the (xt, yt) arrays of these columns and rows when the
+    images are a window of a larger frame (its normalised coordinates)."""
     B = basis(spec) if B is None else B
     H, W = np.shape(ref)
     h = spec.half_width
     C = convolve(ref, B) if C is None else C
     phi = fit_set(ref_mask, sci_mask, ref_var, sci_var, h)
-    xt, yt = norm_coords(W, H)
+    xt, yt = norm_coords(W, H) if coords is None else coords
     sci = np.asarray(sci, np.float64)
     wts = 1.0 / (np.asarray(sci_var, np.float64) + np.asarray(ref_var, np.float64) + (~phi))
     n = n_unknowns(spec)
@@ -419,7 +422,7 @@ def expand_kernel(coeffs, spec, B=None):
     return st, coeffs[:, nb * nP:]
 
 
-def subtract(stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec):
+def subtract(stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec, coords=None):
     """Per output pixel p (kernel evaluated at the output pixel):
 
       K_p = sum_m P_m(p) K_m   (K_m of the solve that owns p)
@@ -430,6 +433,7 @@ def subtract(stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec):
     diff_mask = sci_mask bits, plus EDGE within h of the border, plus FOOT where
     any ref_mask bit is set in the footprint; D = V = 0 wherever diff_mask != 0.
     chi2[s] = sum over the fit set of solve s of D^2/(var_S + var_R).
+    coords: as for normal_equations (a window of a larger frame).
     Returns (D, V, diff_mask, chi2 [n_solves], n_fit [n_solves])."""
     stamps = np.asarray(stamps, np.float64)
     bg = np.atleast_2d(np.asarray(bg, np.float64))
@@ -444,7 +448,7 @@ def subtract(stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, spec):
     kw = 2 * h + 1
     mons = monomials(spec.spatial_degree)
     monb = monomials(spec.bg_degree)
-    xt, yt = norm_coords(W, H)
+    xt, yt = norm_coords(W, H) if coords is None else coords
     Dimg = np.zeros((H, W))
     Vimg = np.zeros((H, W))
     dmask = np.asarray(sci_mask, np.uint8).copy()

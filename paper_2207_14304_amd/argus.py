@@ -30,11 +30,43 @@ SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "arg
            "argus_batch_destroy", "argus_cnn_create", "argus_cnn_destroy",
            "argus_cnn_n_params", "argus_cnn_set_weights", "argus_cnn_get_weights",
            "argus_cnn_get_grads", "argus_cnn_forward", "argus_cnn_train_step",
-           "argus_surrogate_coeffs", "argus_surrogate_select", "argus_extract_stamps")
+           "argus_surrogate_coeffs", "argus_surrogate_select", "argus_extract_stamps",
+           "argus_background", "argus_detect_sources", "argus_coadd_matched",
+           "argus_healpix_tiles", "argus_resample_healpix", "argus_zogy")
 
 
 class Dims(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("pitch", C.c_int64)]
+
+
+class Wcs(C.Structure):
+    """argus_wcs: gnomonic frame geometry (degrees; cd row-major)."""
+    _fields_ = [("ra0", C.c_double), ("dec0", C.c_double), ("crpix1", C.c_double),
+                ("crpix2", C.c_double), ("cd", C.c_double * 4)]
+
+
+def make_wcs(ra0, dec0, crpix1, crpix2, cd) -> Wcs:
+    w = Wcs()
+    w.ra0, w.dec0, w.crpix1, w.crpix2 = float(ra0), float(dec0), float(crpix1), float(crpix2)
+    for i, v in enumerate(np.asarray(cd, np.float64).ravel()):
+        w.cd[i] = float(v)
+    return w
+
+
+def healpix_tiles(wcs: Wcs, width: int, height: int, nside: int = 256, step: int = 32):
+    """argus_healpix_tiles: the (face, I, J) tiles the frame falls in, [n][3] int32."""
+    lib = load()
+    cap = 4096
+    while True:
+        buf = np.zeros((cap, 3), np.int32)
+        n = C.c_int()
+        rc = lib.argus_healpix_tiles(C.byref(wcs), int(width), int(height), int(nside), int(step),
+                                     buf.ctypes.data_as(C.c_void_p), cap, C.byref(n))
+        if rc:
+            raise ArgusError(rc, "argus_healpix_tiles failed")
+        if n.value <= cap:
+            return buf[: n.value].copy()
+        cap = n.value
 
 
 class KernelSpec(C.Structure):
@@ -55,6 +87,8 @@ class Frame(C.Structure):
                 ("width", C.c_int32), ("height", C.c_int32), ("pitch", C.c_int64)]
 
 
+SOURCE_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("xc", np.float32), ("yc", np.float32),
+                         ("snr", np.float32), ("flux", np.float32), ("flux_err", np.float32)])
 CANDIDATE_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("snr", np.float32),
                             ("flux", np.float32), ("flux_err", np.float32)])
 
@@ -103,6 +137,18 @@ def load(path: str = LIB_PATH):
     lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 10
     lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
     lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 15
+    lib.argus_background.argtypes = [vp, Dims, vp, vp, C.c_int, vp, vp, vp]
+    d64 = C.c_double
+    lib.argus_zogy.argtypes = [vp, Dims, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp, vp, C.c_int,
+                               d64, d64, d64, d64, vp, vp, vp, vp, vp]
+    lib.argus_healpix_tiles.argtypes = [C.POINTER(Wcs), C.c_int, C.c_int, C.c_int, C.c_int, vp,
+                                        C.c_int, C.POINTER(C.c_int)]
+    lib.argus_resample_healpix.argtypes = [vp, Dims, vp, vp, vp, C.POINTER(Wcs), C.c_int, C.c_int,
+                                           vp, C.c_int, vp, vp, vp]
+    lib.argus_coadd_matched.argtypes = [vp, Dims, C.c_int, vp, vp, vp, vp, C.c_int, vp, C.c_int,
+                                        vp, vp, vp, vp]
+    lib.argus_detect_sources.argtypes = [vp, Dims, vp, vp, vp, vp, C.c_int, f32, vp, C.c_int, vp,
+                                         vp, vp, C.c_int32, vp]
     lib.argus_detect.argtypes = [vp, Dims, vp, vp, vp, f32, vp, C.c_int, vp, vp, vp, i32, vp]
     lib.argus_batch_plan.argtypes = [vp, C.POINTER(KernelSpec), C.POINTER(Cutout), C.c_int,
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int,
@@ -280,6 +326,82 @@ class Context:
             _ptr(diff_mask, torch.uint8), float(threshold), _ptr(psf, torch.float32),
             int(psf_half), _ptr(snr, torch.float32), _ptr(det_mask, torch.uint8),
             _ptr(cands, torch.uint8), int(capacity), _ptr(n_cands, torch.int32)))
+
+
+def _background(self, cal, mask, box, grid, levels=None, bg_map=None):
+    """argus_background: filtered cell grid (and optionally the raw levels and
+    the full-resolution map) of a calibrated frame."""
+    torch = self._torch
+    self._bind()
+    self._check(self.lib.argus_background(
+        self.h, _dims(cal), _ptr(cal, torch.float32), _ptr(mask, torch.uint8), int(box),
+        _ptr(levels, torch.float32), _ptr(grid, torch.float32), _ptr(bg_map, torch.float32)))
+
+
+def _detect_sources(self, cal, var, mask, grid, box, threshold, psf, psf_half, snr, det_mask,
+                    sources, capacity, n_sources):
+    """argus_detect_sources; sources is a uint8 buffer of capacity * SOURCE_DTYPE.itemsize."""
+    torch = self._torch
+    self._bind()
+    self._check(self.lib.argus_detect_sources(
+        self.h, _dims(cal), _ptr(cal, torch.float32), _ptr(var, torch.float32),
+        _ptr(mask, torch.uint8), _ptr(grid, torch.float32), int(box), float(threshold),
+        _ptr(psf, torch.float32), int(psf_half), _ptr(snr, torch.float32),
+        _ptr(det_mask, torch.uint8), _ptr(sources, torch.uint8), int(capacity),
+        _ptr(n_sources, torch.int32)))
+
+
+def _coadd_matched(self, cals, vars_, masks, psf, psf_half, score, score_var, snr=None,
+                   grids=None, box=64, scales=None):
+    """argus_coadd_matched: psf a device f32 [n][2r+1][2r+1] tensor; grids a
+    list (entries may be None) of background grids; scales host floats."""
+    torch = self._torch
+    self._bind()
+    n = len(cals)
+    arr = C.c_void_p * n
+    g = arr(*[_ptr(x, torch.float32) if x is not None else None for x in (grids or [None] * n)])
+    sc = (C.c_float * n)(*[float(v) for v in scales]) if scales is not None else None
+    self._check(self.lib.argus_coadd_matched(
+        self.h, _dims(score), n, arr(*[_ptr(c, torch.float32) for c in cals]),
+        arr(*[_ptr(v, torch.float32) for v in vars_]), arr(*[_ptr(m, torch.uint8) for m in masks]),
+        g, int(box), _ptr(psf, torch.float32), int(psf_half), sc, _ptr(score, torch.float32),
+        _ptr(score_var, torch.float32), _ptr(snr, torch.float32)))
+
+
+def _resample_healpix(self, cal, var, mask, wcs, nside, m, tiles, out, out_var, out_mask):
+    """argus_resample_healpix: tiles a device int32 [n][3] tensor."""
+    torch = self._torch
+    self._bind()
+    if tiles.dtype != torch.int32 or tiles.dim() != 2 or tiles.shape[1] != 3:
+        raise ValueError("tiles: int32 [n][3]")
+    self._check(self.lib.argus_resample_healpix(
+        self.h, _dims(cal), _ptr(cal, torch.float32), _ptr(var, torch.float32),
+        _ptr(mask, torch.uint8), C.byref(wcs), int(nside), int(m), _ptr(tiles, torch.int32),
+        int(tiles.shape[0]), _ptr(out, torch.float32), _ptr(out_var, torch.float32),
+        _ptr(out_mask, torch.uint8)))
+
+
+def _zogy(self, new, new_mask, ref, ref_mask, origins, L, psf_n, psf_r, psf_half, Fn, Fr, sn, sr,
+          D, snr, flux, mask, pd2=None):
+    """argus_zogy: origins a device int32 [n][2] tensor (x0, y0 per tile)."""
+    torch = self._torch
+    self._bind()
+    if origins.dtype != torch.int32 or origins.dim() != 2 or origins.shape[1] != 2:
+        raise ValueError("origins: int32 [n][2]")
+    self._check(self.lib.argus_zogy(
+        self.h, _dims(new), _ptr(new, torch.float32), _ptr(new_mask, torch.uint8),
+        _ptr(ref, torch.float32), _ptr(ref_mask, torch.uint8), _ptr(origins, torch.int32),
+        int(origins.shape[0]), int(L), _ptr(psf_n, torch.float32), _ptr(psf_r, torch.float32),
+        int(psf_half), float(Fn), float(Fr), float(sn), float(sr), _ptr(D, torch.float32),
+        _ptr(snr, torch.float32), _ptr(flux, torch.float32), _ptr(mask, torch.uint8),
+        _ptr(pd2, torch.float64)))
+
+
+Context.zogy = _zogy
+Context.resample_healpix = _resample_healpix
+Context.coadd_matched = _coadd_matched
+Context.background = _background
+Context.detect_sources = _detect_sources
 
 
 class Batch:

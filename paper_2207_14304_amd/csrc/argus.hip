@@ -1,5 +1,6 @@
 // libargus C ABI: context, workspace, argument validation and dispatch.
 // The operations themselves are specified in include/argus.h.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -292,8 +293,12 @@ int argus_fit_kernel(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *s
     if (rc || !chi2) return rc;
     // second pass over the residuals: D = S - X a at every fit pixel
     if ((rc = launch_expand(ctx, spec, coeffs, stamps, bg))) return rc;
-    return launch_subtract(ctx, dims, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var,
-                           sci_mask, nullptr, nullptr, nullptr, chi2, nullptr, nullptr, nullptr);
+    rc = launch_subtract(ctx, dims, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var,
+                         sci_mask, nullptr, nullptr, nullptr, chi2, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    int n_unk, n_solves;
+    (void)argus_kernel_dims(spec, &n_unk, &n_solves);
+    return launch_chi2_failed(ctx, chi2, status, n_solves);
 }
 
 int argus_expand_kernel(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,
@@ -344,6 +349,113 @@ int argus_detect(argus_ctx *ctx, argus_dims dims, const float *diff, const float
         return argus_fail(ctx, ARGUS_EINVAL, "threshold is NaN");
     return launch_detect(ctx, dims, diff, diff_var, diff_mask, threshold, psf, psf_half, snr,
                          det_mask, cands, capacity, n_cands);
+}
+
+int argus_background(argus_ctx *ctx, argus_dims dims, const float *cal, const uint8_t *mask,
+                     int box, float *levels, float *grid, float *map) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (!cal || !mask || !grid) return argus_fail(ctx, ARGUS_EINVAL, "argus_background: null pointer");
+    if (box < 4 || box > 64) return argus_fail(ctx, ARGUS_ESHAPE, "box %d not in 4..64", box);
+    return launch_background(ctx, dims, cal, mask, box, levels, grid, map);
+}
+
+int argus_detect_sources(argus_ctx *ctx, argus_dims dims, const float *cal, const float *var,
+                         const uint8_t *mask, const float *grid, int box, float threshold,
+                         const float *psf, int psf_half, float *snr, uint8_t *det_mask,
+                         argus_source *sources, int32_t capacity, int32_t *n_sources) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (!cal || !var || !mask || !grid || !psf || !det_mask || !n_sources)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_detect_sources: null pointer");
+    if (capacity < 0 || (capacity > 0 && !sources))
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_detect_sources: capacity < 0 or null list");
+    if (box < 4 || box > 64) return argus_fail(ctx, ARGUS_ESHAPE, "box %d not in 4..64", box);
+    if (psf_half < 0 || psf_half > 15)
+        return argus_fail(ctx, ARGUS_ESHAPE, "psf_half %d not in 0..15", psf_half);
+    if (!(threshold == threshold)) return argus_fail(ctx, ARGUS_EINVAL, "threshold is NaN");
+    return launch_detect_sources(ctx, dims, cal, var, mask, grid, box, threshold, psf, psf_half,
+                                 snr, det_mask, sources, capacity, n_sources);
+}
+
+int argus_coadd_matched(argus_ctx *ctx, argus_dims dims, int n_frames,
+                        const float *const *cal, const float *const *var,
+                        const uint8_t *const *mask, const float *const *grids, int box,
+                        const float *psf, int psf_half, const float *scales,
+                        float *score, float *score_var, float *snr) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (n_frames < 1 || n_frames > ARGUS_MAX_FRAMES)
+        return argus_fail(ctx, ARGUS_EINVAL, "n_frames %d not in 1..%d", n_frames, ARGUS_MAX_FRAMES);
+    if (!cal || !var || !mask || !psf || !score || !score_var)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_coadd_matched: null pointer");
+    bool any_grid = false;
+    for (int j = 0; j < n_frames; ++j) {
+        if (!cal[j] || !var[j] || !mask[j])
+            return argus_fail(ctx, ARGUS_EINVAL, "argus_coadd_matched: null plane of frame %d", j);
+        any_grid |= grids && grids[j];
+    }
+    if (psf_half < 1 || psf_half > 10)
+        return argus_fail(ctx, ARGUS_ESHAPE, "psf_half %d not in 1..10", psf_half);
+    if (any_grid && (box < 4 || box > 64))
+        return argus_fail(ctx, ARGUS_ESHAPE, "box %d not in 4..64", box);
+    return launch_coadd_matched(ctx, dims, n_frames, cal, var, mask, grids, box, psf, psf_half,
+                                scales, score, score_var, snr);
+}
+
+int argus_healpix_tiles(const argus_wcs *wcs, int width, int height, int nside, int step,
+                        int32_t *tiles, int capacity, int *n_tiles) {
+    if (!wcs || !n_tiles || (capacity > 0 && !tiles) || capacity < 0) return ARGUS_EINVAL;
+    if (width < 1 || height < 1 || nside < 1 || nside > (1 << 20) || step < 1) return ARGUS_EINVAL;
+    return healpix_tiles(wcs, width, height, nside, step, tiles, capacity, n_tiles);
+}
+
+int argus_resample_healpix(argus_ctx *ctx, argus_dims dims, const float *cal, const float *var,
+                           const uint8_t *mask, const argus_wcs *wcs, int nside, int m,
+                           const int32_t *tiles, int n_tiles, float *out, float *out_var,
+                           uint8_t *out_mask) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (!cal || !var || !mask || !wcs || !tiles || !out || !out_var || !out_mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_resample_healpix: null pointer");
+    if (nside < 1 || nside > (1 << 20) || m < 1 || m > 4096 || n_tiles < 1 || n_tiles > 65535)
+        return argus_fail(ctx, ARGUS_ESHAPE, "nside %d, m %d or n_tiles %d out of range", nside, m,
+                          n_tiles);
+    return launch_resample_healpix(ctx, dims, cal, var, mask, wcs, nside, m, tiles, n_tiles, out,
+                                   out_var, out_mask);
+}
+
+int argus_zogy(argus_ctx *ctx, argus_dims dims, const float *new_img, const uint8_t *new_mask,
+               const float *ref, const uint8_t *ref_mask, const int32_t *origins, int n_tiles,
+               int L, const float *psf_n, const float *psf_r, int psf_half, double Fn, double Fr,
+               double sn, double sr, float *D, float *snr, float *flux, uint8_t *mask,
+               double *pd2) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if (!new_img || !new_mask || !ref || !ref_mask || !origins || !psf_n || !psf_r || !D || !snr ||
+        !flux || !mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_zogy: null pointer");
+    if (L < 64 || L > 1024 || (L & (L - 1)) != 0)
+        return argus_fail(ctx, ARGUS_ESHAPE, "tile side %d is not a power of two in 64..1024", L);
+    if (psf_half < 1 || psf_half > 15 || 4 * psf_half + 2 > L)
+        return argus_fail(ctx, ARGUS_ESHAPE, "psf_half %d not in 1..15 or too large for L", psf_half);
+    if (n_tiles < 1 || n_tiles > 65535)
+        return argus_fail(ctx, ARGUS_ESHAPE, "n_tiles %d not in 1..65535", n_tiles);
+    if (!(Fn > 0) || !(Fr > 0) || !(sn >= 0) || !(sr >= 0) || !(sn > 0 || sr > 0) ||
+        !isfinite(Fn) || !isfinite(Fr) || !isfinite(sn) || !isfinite(sr))
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_zogy: bad zero points or noise sigmas");
+    return launch_zogy(ctx, dims, new_img, new_mask, ref, ref_mask, origins, n_tiles, L, psf_n,
+                       psf_r, psf_half, Fn, Fr, sn, sr, D, snr, flux, mask, pd2);
 }
 
 }  // extern "C"

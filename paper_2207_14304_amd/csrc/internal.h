@@ -110,6 +110,8 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                double *coeffs, int64_t *n_fit, int32_t *status);
 int launch_expand(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,
                   float *stamps, float *bg);
+// chi2[s] = NaN where status[s] != ARGUS_OK (n solves)
+int launch_chi2_failed(argus_ctx *ctx, double *chi2, const int32_t *status, int n);
 int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                     const float *stamps, const float *bg, const float *ref,
                     const float *ref_var, const uint8_t *ref_mask, const float *sci,
@@ -119,6 +121,30 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
 int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
                   const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
                   uint8_t *det, argus_candidate *cands, int32_t cap, int32_t *n_cands);
+
+int launch_background(argus_ctx *ctx, argus_dims d, const float *cal, const uint8_t *mask, int box,
+                      float *levels, float *grid, float *map);
+int launch_detect_sources(argus_ctx *ctx, argus_dims d, const float *cal, const float *var,
+                          const uint8_t *mask, const float *grid, int box, float thr,
+                          const float *psf, int r, float *snr, uint8_t *det, argus_source *srcs,
+                          int32_t cap, int32_t *n_srcs);
+
+int launch_coadd_matched(argus_ctx *ctx, argus_dims d, int n, const float *const *cal,
+                         const float *const *var, const uint8_t *const *mask,
+                         const float *const *grids, int box, const float *psf, int r,
+                         const float *scales, float *S, float *Var, float *snr);
+
+int launch_resample_healpix(argus_ctx *ctx, argus_dims d, const float *cal, const float *var,
+                            const uint8_t *mask, const argus_wcs *wcs, int nside, int m,
+                            const int32_t *tiles, int n_tiles, float *out, float *out_var,
+                            uint8_t *out_mask);
+int healpix_tiles(const argus_wcs *wcs, int W, int H, int nside, int step, int32_t *tiles,
+                  int capacity, int *n_tiles);
+
+int launch_zogy(argus_ctx *ctx, argus_dims d, const float *N, const uint8_t *mn, const float *R,
+                const uint8_t *mr, const int32_t *origins, int n, int L, const float *psf_n,
+                const float *psf_r, int r, double Fn, double Fr, double sn, double sr, float *D,
+                float *snr, float *flux, uint8_t *mask, double *pd2_out);
 
 #define ARGUS_HIP_CHECK(ctx, call)                                                 \
     do {                                                                           \

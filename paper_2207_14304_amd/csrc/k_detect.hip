@@ -9,7 +9,15 @@
 //   tiles in parallel, then the tile totals) -> raster-order offsets.
 // detect_emit: one wave per segment with candidates writes them in raster
 //   order at their offsets and measures the PSF flux in FP64.
+//
+// Source mode (argus_detect_sources): the same kernels on a calibrated frame,
+// with D = cal - background evaluated from the filtered cell grid per pixel,
+// V the calibration's variance and its mask; sources also get the centroid
+// of max(D, 0) over the unmasked in-image 3 x 3 neighbourhood.
+#include <algorithm>
+
 #include "internal.h"
+#include "background.h"
 
 namespace {
 
@@ -28,7 +36,9 @@ struct DetArgs {
     int32_t *tile_off;         // [ntile]
     const float *psf;
     argus_candidate *cands;
+    argus_source *srcs;
     int32_t *n_cands;
+    BgGrid bg;                 // source mode: D = diff - bg(x, y)
     int64_t pitch;
     int W, H, nsx, nseg, ntile, r, cap;
     int vec;                   // 16-byte aligned planes, pitch % 4 == 0
@@ -37,18 +47,26 @@ struct DetArgs {
 
 // SNR of one pixel: D / sqrt(V) where the pixel is unmasked and V > 0, else 0;
 // off-image pixels are -inf for the neighbour comparisons.
+template <bool SRC>
+__device__ __forceinline__ float d_at(const DetArgs &a, int64_t o, int x, int y) {
+    if constexpr (SRC) return a.diff[o] - bg_at(a.bg, x, y);
+    return a.diff[o];
+}
+
+template <bool SRC>
 __device__ __forceinline__ float snr_at(const DetArgs &a, int x, int y) {
     if (x < 0 || x >= a.W || y < 0 || y >= a.H) return -__builtin_inff();
     int64_t o = (int64_t)y * a.pitch + x;
     float V = a.dvar[o];
     if (a.dmask[o] != 0 || !(V > 0.f)) return 0.f;
-    return a.diff[o] * __builtin_amdgcn_rsqf(V);
+    return d_at<SRC>(a, o, x, y) * __builtin_amdgcn_rsqf(V);
 }
 
 __device__ __forceinline__ float snr_of(float D, float V, uint32_t m) {
     return (m != 0 || !(V > 0.f)) ? 0.f : D * __builtin_amdgcn_rsqf(V);
 }
 
+template <bool SRC>
 __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
     __shared__ __align__(16) float s[ROWS + 2][LW];
     const int sx = blockIdx.x, y0 = blockIdx.y * ROWS, tid = threadIdx.x;
@@ -82,8 +100,16 @@ __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
                     v = make_float4(-__builtin_inff(), -__builtin_inff(), -__builtin_inff(),
                                     -__builtin_inff());
                 } else {
-                    const float4 D = Dv[j], V = Vv[j];
+                    float4 D = Dv[j];
+                    const float4 V = Vv[j];
                     const uint32_t m = Mv[j];
+                    if constexpr (SRC) {
+                        const int x = x0 + 4 * ch;
+                        D.x -= bg_at(a.bg, x, y);
+                        D.y -= bg_at(a.bg, x + 1, y);
+                        D.z -= bg_at(a.bg, x + 2, y);
+                        D.w -= bg_at(a.bg, x + 3, y);
+                    }
                     v = make_float4(snr_of(D.x, V.x, m & 0xffu),
                                     snr_of(D.y, V.y, (m >> 8) & 0xffu),
                                     snr_of(D.z, V.z, (m >> 16) & 0xffu),
@@ -96,14 +122,14 @@ __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
         for (int i = tid; i < NCH; i += NTHR) {
             const int row = i / (SEG / 4), ch = i % (SEG / 4);
             const int y = y0 - 1 + row, x = x0 + 4 * ch;
-            const float4 v = make_float4(snr_at(a, x, y), snr_at(a, x + 1, y),
-                                         snr_at(a, x + 2, y), snr_at(a, x + 3, y));
+            const float4 v = make_float4(snr_at<SRC>(a, x, y), snr_at<SRC>(a, x + 1, y),
+                                         snr_at<SRC>(a, x + 2, y), snr_at<SRC>(a, x + 3, y));
             *(float4 *)&s[row][4 + 4 * ch] = v;
         }
     }
     if (tid < 2 * (ROWS + 2)) {
         const int row = tid >> 1, side = tid & 1;
-        s[row][side ? 4 + SEG : 3] = snr_at(a, side ? x0 + SEG : x0 - 1, y0 - 1 + row);
+        s[row][side ? 4 + SEG : 3] = snr_at<SRC>(a, side ? x0 + SEG : x0 - 1, y0 - 1 + row);
     }
     __syncthreads();
     const int lane = tid & 63, w = tid >> 6;
@@ -201,60 +227,105 @@ __global__ __launch_bounds__(64) void scan_top_kernel(DetArgs a) {
     if (lane == 0) *a.n_cands = carry;
 }
 
+template <bool SRC>
 __global__ __launch_bounds__(NTHR) void detect_emit_kernel(DetArgs a) {
     const int lane = threadIdx.x & 63;
-    const int seg = blockIdx.x * (NTHR / 64) + (threadIdx.x >> 6);
-    if (seg >= a.nseg || a.counts[seg] == 0) return;
-    int idx = a.tile_off[seg / STILE] + a.local[seg];
-    const int y = seg / a.nsx, x0 = (seg % a.nsx) * SEG;
-    const int64_t orow = (int64_t)y * a.pitch;
-    const int K = 2 * a.r + 1;
-    for (int c0 = 0; c0 < SEG && idx < a.cap; c0 += 64) {
-        const int x = x0 + c0 + lane;
-        const bool isc = x < a.W && (a.det[orow + x] & ARGUS_CAND);
-        uint64_t bal = __ballot(isc);
-        while (bal && idx < a.cap) {
-            const int l = __builtin_ctzll(bal);
-            bal &= bal - 1;
-            const int cx = x0 + c0 + l;
-            // PSF-weighted flux over unmasked in-image pixels of the window
-            double q = 0.0, f = 0.0;
-            for (int t = lane; t < K * K; t += 64) {
-                int xx = cx + t % K - a.r, yy = y + t / K - a.r;
-                if (xx < 0 || xx >= a.W || yy < 0 || yy >= a.H) continue;
-                int64_t o = (int64_t)yy * a.pitch + xx;
-                float V = a.dvar[o];
-                if (a.dmask[o] != 0 || !(V > 0.f)) continue;
-                double p = (double)a.psf[t];
-                q += p * p / (double)V;
-                f += p * (double)a.diff[o] / (double)V;
+    // a wave walks segments with a stride of all waves (most hold no candidate)
+    const int nw = gridDim.x * (NTHR / 64);
+    for (int seg = blockIdx.x * (NTHR / 64) + (threadIdx.x >> 6); seg < a.nseg; seg += nw) {
+        if (a.counts[seg] == 0) continue;
+        int idx = a.tile_off[seg / STILE] + a.local[seg];
+        const int y = seg / a.nsx, x0 = (seg % a.nsx) * SEG;
+        const int64_t orow = (int64_t)y * a.pitch;
+        const int K = 2 * a.r + 1;
+        for (int c0 = 0; c0 < SEG && idx < a.cap; c0 += 64) {
+            const int x = x0 + c0 + lane;
+            const bool isc = x < a.W && (a.det[orow + x] & ARGUS_CAND);
+            uint64_t bal = __ballot(isc);
+            while (bal && idx < a.cap) {
+                const int l = __builtin_ctzll(bal);
+                bal &= bal - 1;
+                const int cx = x0 + c0 + l;
+                // PSF-weighted flux over unmasked in-image pixels of the window
+                double q = 0.0, f = 0.0;
+                for (int t = lane; t < K * K; t += 64) {
+                    int xx = cx + t % K - a.r, yy = y + t / K - a.r;
+                    if (xx < 0 || xx >= a.W || yy < 0 || yy >= a.H) continue;
+                    int64_t o = (int64_t)yy * a.pitch + xx;
+                    float V = a.dvar[o];
+                    if (a.dmask[o] != 0 || !(V > 0.f)) continue;
+                    double p = (double)a.psf[t];
+                    q += p * p / (double)V;
+                    f += p * (double)d_at<SRC>(a, o, xx, yy) / (double)V;
+                }
+                // source centroid: max(D, 0) over the unmasked in-image 3 x 3
+                double cs = 0.0, cxs = 0.0, cys = 0.0;
+                if constexpr (SRC) {
+                    if (lane < 9) {
+                        const int u = lane % 3 - 1, v = lane / 3 - 1, xx = cx + u, yy = y + v;
+                        if (xx >= 0 && xx < a.W && yy >= 0 && yy < a.H) {
+                            const int64_t o = (int64_t)yy * a.pitch + xx;
+                            const float V = a.dvar[o];
+                            if (a.dmask[o] == 0 && V > 0.f) {
+                                const double d = fmax((double)d_at<SRC>(a, o, xx, yy), 0.0);
+                                cs = d;
+                                cxs = u * d;
+                                cys = v * d;
+                            }
+                        }
+                    }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    q += __shfl_xor(q, off);
+                    f += __shfl_xor(f, off);
+                    if constexpr (SRC) {
+                        cs += __shfl_xor(cs, off);
+                        cxs += __shfl_xor(cxs, off);
+                        cys += __shfl_xor(cys, off);
+                    }
+                }
+                if (lane == 0) {
+                    const float fl = q > 0.0 ? (float)(f / q) : __builtin_nanf("");
+                    const float fe = q > 0.0 ? (float)(1.0 / sqrt(q)) : __builtin_nanf("");
+                    if constexpr (SRC) {
+                        argus_source c;
+                        c.x = cx;
+                        c.y = y;
+                        c.xc = cs > 0.0 ? (float)(cx + cxs / cs) : __builtin_nanf("");
+                        c.yc = cs > 0.0 ? (float)(y + cys / cs) : __builtin_nanf("");
+                        c.snr = snr_at<SRC>(a, cx, y);
+                        c.flux = fl;
+                        c.flux_err = fe;
+                        a.srcs[idx] = c;
+                    } else {
+                        argus_candidate c;
+                        c.x = cx;
+                        c.y = y;
+                        c.snr = snr_at<SRC>(a, cx, y);
+                        c.flux = fl;
+                        c.flux_err = fe;
+                        a.cands[idx] = c;
+                    }
+                }
+                ++idx;
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                q += __shfl_xor(q, off);
-                f += __shfl_xor(f, off);
-            }
-            if (lane == 0) {
-                argus_candidate c;
-                c.x = cx;
-                c.y = y;
-                c.snr = snr_at(a, cx, y);
-                c.flux = q > 0.0 ? (float)(f / q) : __builtin_nanf("");
-                c.flux_err = q > 0.0 ? (float)(1.0 / sqrt(q)) : __builtin_nanf("");
-                a.cands[idx] = c;
-            }
-            ++idx;
         }
     }
 }
 
 }  // namespace
 
-int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
-                  const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
-                  uint8_t *det, argus_candidate *cands, int32_t cap, int32_t *n_cands) {
+namespace {
+
+int launch_detect_any(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
+                      const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
+                      uint8_t *det, argus_candidate *cands, argus_source *srcs, const float *grid,
+                      int box, int32_t cap, int32_t *n_cands) {
+    const bool src = grid != nullptr;
     DetArgs a;
     a.diff = diff; a.dvar = dvar; a.dmask = dmask; a.snr = snr; a.det = det;
-    a.psf = psf; a.cands = cands; a.n_cands = n_cands;
+    a.psf = psf; a.cands = cands; a.srcs = srcs; a.n_cands = n_cands;
+    a.bg = src ? make_bg_grid(grid, box, d.width, d.height) : BgGrid{};
     a.pitch = d.pitch; a.W = d.width; a.H = d.height;
     a.nsx = (d.width + SEG - 1) / SEG;
     a.nseg = a.nsx * d.height;
@@ -272,13 +343,40 @@ int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *
     a.tile_sum = w + 2 * (size_t)a.nseg;
     a.tile_off = a.tile_sum + a.ntile;
     argus_time_begin(ctx);
-    hipLaunchKernelGGL(detect_map_kernel, dim3(a.nsx, (d.height + ROWS - 1) / ROWS), dim3(NTHR), 0,
-                       ctx->stream, a);
+    const dim3 mg(a.nsx, (d.height + ROWS - 1) / ROWS);
+    if (src)
+        hipLaunchKernelGGL(detect_map_kernel<true>, mg, dim3(NTHR), 0, ctx->stream, a);
+    else
+        hipLaunchKernelGGL(detect_map_kernel<false>, mg, dim3(NTHR), 0, ctx->stream, a);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
-    argus_time_end(ctx, "detect_map");
+    argus_time_end(ctx, src ? "source_map" : "detect_map");
+    argus_time_begin(ctx);
     hipLaunchKernelGGL(scan_tiles_kernel, dim3(a.ntile), dim3(NTHR), 0, ctx->stream, a);
     hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(64), 0, ctx->stream, a);
-    hipLaunchKernelGGL(detect_emit_kernel, dim3((a.nseg + 3) / 4), dim3(NTHR), 0, ctx->stream, a);
+    // enough waves to fill the device a few times over; each walks segments
+    const int eblocks = std::max(1, std::min((a.nseg + 3) / 4, 8 * std::max(ctx->n_cu, 1)));
+    if (src)
+        hipLaunchKernelGGL(detect_emit_kernel<true>, dim3(eblocks), dim3(NTHR), 0, ctx->stream, a);
+    else
+        hipLaunchKernelGGL(detect_emit_kernel<false>, dim3(eblocks), dim3(NTHR), 0, ctx->stream, a);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    argus_time_end(ctx, src ? "source_emit" : "detect_emit");
     return ARGUS_OK;
+}
+
+}  // namespace
+
+int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
+                  const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
+                  uint8_t *det, argus_candidate *cands, int32_t cap, int32_t *n_cands) {
+    return launch_detect_any(ctx, d, diff, dvar, dmask, thr, psf, r, snr, det, cands, nullptr,
+                             nullptr, 0, cap, n_cands);
+}
+
+int launch_detect_sources(argus_ctx *ctx, argus_dims d, const float *cal, const float *var,
+                          const uint8_t *mask, const float *grid, int box, float thr,
+                          const float *psf, int r, float *snr, uint8_t *det, argus_source *srcs,
+                          int32_t cap, int32_t *n_srcs) {
+    return launch_detect_any(ctx, d, cal, var, mask, thr, psf, r, snr, det, nullptr, srcs, grid,
+                             box, cap, n_srcs);
 }

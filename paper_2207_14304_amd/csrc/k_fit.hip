@@ -558,6 +558,20 @@ int launch_fit(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec, cons
     return ARGUS_OK;
 }
 
+namespace {
+__global__ void chi2_failed_kernel(double *chi2, const int32_t *status, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && status[i] != ARGUS_OK) chi2[i] = __builtin_nan("");
+}
+}  // namespace
+
+int launch_chi2_failed(argus_ctx *ctx, double *chi2, const int32_t *status, int n) {
+    hipLaunchKernelGGL(chi2_failed_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, chi2,
+                       status, n);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    return ARGUS_OK;
+}
+
 int launch_expand(argus_ctx *ctx, const argus_kernel_spec *spec, const double *coeffs,
                   float *stamps, float *bg) {
     int n, ns;

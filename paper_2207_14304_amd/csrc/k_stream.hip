@@ -27,17 +27,29 @@ struct CalArgs {
 // (raw is an integer below 2^16, dark a float); the division by the flat is a
 // multiplication by its FP64 reciprocal, computed once per pixel (and shared
 // by every frame of a fused calibration), which is within one FP64 ulp of the
-// quotient.
+// quotient (the FP32 results are those of the quotient except where it lies
+// within an FP64 ulp of an FP32 rounding boundary).
 struct CalPix {
     double rf, rf2;            // 1 / flat, its square
     double d;
     bool bad;
 };
 
+// 1/x in FP64 for a positive normal x: the hardware estimate refined by two
+// Newton steps (each doubles the correct bits), within one ulp of the quotient.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 __device__ __forceinline__ CalPix cal_pix(float d, float f, uint8_t b) {
     CalPix p;
     p.bad = (b != 0) || !(f > 0.f) || !__builtin_isfinite(f) || !__builtin_isfinite(d);
-    p.rf = 1.0 / (double)f;
+    // a BAD pixel's values are discarded: any positive operand will do
+    p.rf = rcp64(p.bad ? 1.0 : (double)f);
     p.rf2 = p.rf * p.rf;
     p.d = (double)d;
     return p;
@@ -187,8 +199,10 @@ __device__ __forceinline__ void coadd_one(const CoaddArgs &a, const float (&x)[N
             sv += (double)v[i];
         }
     }
-    ref = cnt ? (float)(sx / cnt) : 0.f;
-    rv = cnt ? (float)(sv / ((double)cnt * cnt)) : 0.f;
+    // 1/cnt in FP64 (exact for 1, 2, 4, 8; within one FP64 ulp otherwise)
+    const double ic = cnt ? rcp64((double)cnt) : 0.0;
+    ref = (float)(sx * ic);
+    rv = (float)(sv * (ic * ic));
     rm = (S0 == 0u ? ARGUS_NODATA : 0u) | (sat ? ARGUS_SAT : 0u);
     nu = (uint8_t)cnt;
 }

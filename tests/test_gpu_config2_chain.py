@@ -20,7 +20,8 @@ difference mask bit-exact; the difference image RMS of (D_gpu - D_oracle)/sigma
 near-tie; V relative <= 1e-5; chi^2/dof relative <= 1e-5; the SNR map
 within the difference image's bars (it is D/sigma); the candidates equal
 except where the oracle's SNR is within 1e-3 of the threshold or of an
-8-neighbour's (counted), their fluxes relative <= 1e-4.
+8-neighbour's (counted), their fluxes within 1e-4 relative plus 1e-2 of
+their error (the difference image's max bar carried through the PSF sum).
 """
 import numpy as np
 import pytest
@@ -152,5 +153,8 @@ def test_detection(chain):
     gi = {(int(c["x"]), int(c["y"])): c for c in gc}
     oi = {(int(c["x"]), int(c["y"])): c for c in oc}
     assert len(both) >= 10
+    # a chained flux carries the difference image's error over the PSF window:
+    # up to the max D bar (1e-2 sigma) in units of its error, beside T7's 1e-4
     for k in both:
-        assert abs(gi[k]["flux"] / oi[k]["flux"] - 1) <= 1e-4, (k, gi[k], oi[k])
+        tol = 1e-4 * abs(oi[k]["flux"]) + 1e-2 * oi[k]["flux_err"]
+        assert abs(gi[k]["flux"] - oi[k]["flux"]) <= tol, (k, gi[k], oi[k])

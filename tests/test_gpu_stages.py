@@ -6,8 +6,9 @@ padded pitches and several tiles.  Tolerances:
 * coadd: n_used and masks bit-exact, ref/ref_var within 4 ulp;
 * subtraction: RMS of (D_gpu - D_oracle)/sqrt(V) <= 1e-4 and max <= 1e-2,
   V relative <= 1e-5, masks bit-exact, chi^2 relative <= 1e-5;
-* kernel fit: stamps max|dK|/max|K| <= 1e-4 (FP32 products, FP64 sums),
-  chi^2/dof relative <= 1e-5, n_fit exact;
+* kernel fit: stamps max|dK|/max|K| <= 1e-4 on noisy data and 2e-3 for the
+  exact recovery of sparse noise-free fields (FP32 products, FP64 sums; FP64
+  moments 1e-5 and 2e-5), chi^2/dof relative <= 1e-5, n_fit exact;
 * detection: DET/CAND bit-exact away from |SNR - threshold| <= 1e-3, SNR
   absolute <= 1e-4, candidate fluxes relative <= 1e-4.
 """
@@ -257,7 +258,7 @@ def test_subtract_delta_identity(ctx):
 # these sparse fields (a numpy emulation of the same arithmetic gives 1.2e-3).
 # FP64 MFMA removes that floor.  (The BF16x3 split keeps ~16 bits per product,
 # which leaves sparse noise-free tiles indefinite; it is judged on noisy data.)
-EXACT_STAMP_TOL = {argus.FP32: 3e-3, argus.FP64: 2e-5}
+EXACT_STAMP_TOL = {argus.FP32: 2e-3, argus.FP64: 2e-5}     # measured <= 6.1e-4, 1.0e-6
 
 
 def _fit(ctx, spec, planes):
@@ -315,7 +316,8 @@ def test_fit_exact_recovery(ctx, D, mode, tiles, prec):
     assert np.allclose(co[:, 0], [a[0] for a in a_true], rtol=1e-5)
 
 
-NOISY_STAMP_TOL = {argus.FP32: 2e-4, argus.FP64: 1e-5, argus.BF16X3: 2e-2}
+# measured <= 5.7e-5 (FP32), 3.5e-6 (FP64), 1.9e-3 (BF16x3)
+NOISY_STAMP_TOL = {argus.FP32: 1e-4, argus.FP64: 1e-5, argus.BF16X3: 2e-2}
 NOISY_CHI2_TOL = {argus.FP32: 1e-6, argus.FP64: 1e-8, argus.BF16X3: 1e-4}
 
 
