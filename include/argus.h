@@ -241,6 +241,28 @@ int argus_subtract(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spe
                    float *diff, float *diff_var, uint8_t *diff_mask,
                    double *chi2, int64_t *n_chi2, double *sum_wd, double *sum_w);
 
+/* ---- subtraction without allocation --------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, outputs and errors as argus_subtract, bit-identical
+ * results, but the per-block partial sums of chi2 / n_chi2 / sum_wd / sum_w
+ * live in a fixed scratch array of the library (2 MiB per device, held until
+ * the process ends) instead of the ctx workspace, and the call performs no
+ * hipMalloc, hipFree or other allocation (nor per-kernel timing records).
+ * Limit: the frame (or, PER_TILE, the tiles) may need at most 65536 blocks of
+ * 128 x 16 output pixels (ceil(w/128) * ceil(h/16) summed over the solves, w
+ * and h a solve's region size; a full 9576 x 6388 frame needs 30000);
+ * larger inputs return ARGUS_ESHAPE.  Every call on one GPU shares that
+ * GPU's scratch: calls that overlap in time on one GPU (other streams, other
+ * contexts, other host threads) race and must be ordered by the caller.
+ * Nothing needs clearing between calls: every block writes its partials. */
+int argus_subtract_noalloc(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
+                           const float *stamps, const float *bg,
+                           const float *ref, const float *ref_var, const uint8_t *ref_mask,
+                           const float *sci, const float *sci_var, const uint8_t *sci_mask,
+                           float *diff, float *diff_var, uint8_t *diff_mask,
+                           double *chi2, int64_t *n_chi2, double *sum_wd, double *sum_w);
+
 /* ---- detection (Transient Alerts: candidates from the subtraction) --------
  * snr = D/sqrt(V) where diff_mask == 0 and V > 0, else 0 (f32, nullable);
  * det_mask = DET where snr >= threshold, | CAND where additionally snr is

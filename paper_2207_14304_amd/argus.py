@@ -26,7 +26,7 @@ SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "arg
            "argus_ctx_set_timing", "argus_kernel_time_ms", "argus_calibrate", "argus_coadd",
            "argus_calibrate_coadd",
            "argus_kernel_dims", "argus_fit_kernel", "argus_expand_kernel", "argus_subtract",
-           "argus_detect", "argus_batch_plan", "argus_batch_run", "argus_batch_info",
+           "argus_subtract_noalloc", "argus_detect", "argus_batch_plan", "argus_batch_run", "argus_batch_info",
            "argus_batch_destroy", "argus_cnn_create", "argus_cnn_destroy",
            "argus_cnn_n_params", "argus_cnn_set_weights", "argus_cnn_get_weights",
            "argus_cnn_get_grads", "argus_cnn_forward", "argus_cnn_train_step",
@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
     lib.argus_fit_kernel.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 10
     lib.argus_expand_kernel.argtypes = [vp, C.POINTER(KernelSpec), vp, vp, vp]
     lib.argus_subtract.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 15
+    lib.argus_subtract_noalloc.argtypes = [vp, Dims, C.POINTER(KernelSpec)] + [vp] * 15
     lib.argus_background.argtypes = [vp, Dims, vp, vp, C.c_int, vp, vp, vp]
     d64 = C.c_double
     lib.argus_zogy.argtypes = [vp, Dims, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp, vp, C.c_int,
@@ -305,10 +306,14 @@ class Context:
             _ptr(bg, torch.float32)))
 
     def subtract(self, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var, sci_mask, diff,
-                 diff_var, diff_mask, chi2=None, n_chi2=None, sum_wd=None, sum_w=None):
+                 diff_var, diff_mask, chi2=None, n_chi2=None, sum_wd=None, sum_w=None,
+                 noalloc=False):
+        """argus_subtract, or with noalloc=True argus_subtract_noalloc (same
+        results; partial sums in the library's fixed scratch, no allocation)."""
         torch = self._torch
         self._bind()
-        self._check(self.lib.argus_subtract(
+        fn = self.lib.argus_subtract_noalloc if noalloc else self.lib.argus_subtract
+        self._check(fn(
             self.h, _dims(ref), C.byref(spec), _ptr(stamps, torch.float32),
             _ptr(bg, torch.float32), _ptr(ref, torch.float32), _ptr(ref_var, torch.float32),
             _ptr(ref_mask, torch.uint8), _ptr(sci, torch.float32), _ptr(sci_var, torch.float32),

@@ -97,6 +97,11 @@ int argus_ctx_create(int device, argus_ctx **out) {
         delete c;
         return ARGUS_ENOMEM;
     }
+    if (subtract_scratch_init(c) != ARGUS_OK) {
+        (void)hipFree(c->tables);
+        delete c;
+        return ARGUS_EHIP;
+    }
     *out = c;
     return ARGUS_OK;
 }
@@ -329,6 +334,27 @@ int argus_subtract(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spe
         return argus_fail(ctx, ARGUS_ESHAPE, "more tiles than pixels");
     return launch_subtract(ctx, dims, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var,
                            sci_mask, diff, diff_var, diff_mask, chi2, n_chi2, sum_wd, sum_w);
+}
+
+int argus_subtract_noalloc(argus_ctx *ctx, argus_dims dims, const argus_kernel_spec *spec,
+                           const float *stamps, const float *bg, const float *ref,
+                           const float *ref_var, const uint8_t *ref_mask, const float *sci,
+                           const float *sci_var, const uint8_t *sci_mask, float *diff,
+                           float *diff_var, uint8_t *diff_mask, double *chi2, int64_t *n_chi2,
+                           double *sum_wd, double *sum_w) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    int rc = check_dims(ctx, dims);
+    if (rc) return rc;
+    if ((rc = check_spec(ctx, spec))) return rc;
+    if (!stamps || !bg || !ref || !ref_var || !ref_mask || !sci || !sci_var || !sci_mask ||
+        !diff || !diff_var || !diff_mask)
+        return argus_fail(ctx, ARGUS_EINVAL, "argus_subtract_noalloc: null pointer");
+    if (spec->tiles_x > dims.width || spec->tiles_y > dims.height)
+        return argus_fail(ctx, ARGUS_ESHAPE, "more tiles than pixels");
+    return launch_subtract(ctx, dims, spec, stamps, bg, ref, ref_var, ref_mask, sci, sci_var,
+                           sci_mask, diff, diff_var, diff_mask, chi2, n_chi2, sum_wd, sum_w,
+                           true);
 }
 
 int argus_detect(argus_ctx *ctx, argus_dims dims, const float *diff, const float *diff_var,

@@ -15,6 +15,10 @@
 #define ARGUS_MAX_PLANES 16          // (gaussian, x-power) row-filter planes
 #define ARGUS_MAX_D      2           // spatial degree
 #define ARGUS_MAX_FRAMES 8           // coadd inputs
+#define ARGUS_MAX_DEVICES 64         // devices with a scratch address table entry
+// blocks of 128x16 output pixels whose partial sums fit the fixed scratch of
+// argus_subtract_noalloc (4 doubles each: 2 MiB per device)
+#define ARGUS_NOALLOC_MAX_BLOCKS 65536
 
 // Device-resident basis tables, laid out in one buffer (floats unless noted).
 //   rowf [ARGUS_MAX_PLANES][32]  : exp(-u^2/2s^2) u^i, index u+h
@@ -117,7 +121,10 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                     const float *ref_var, const uint8_t *ref_mask, const float *sci,
                     const float *sci_var, const uint8_t *sci_mask, float *diff,
                     float *diff_var, uint8_t *diff_mask, double *chi2, int64_t *n_chi2,
-                    double *sum_wd, double *sum_w);
+                    double *sum_wd, double *sum_w, bool noalloc = false);
+// device address of the fixed scratch of argus_subtract_noalloc for
+// ctx->device (which must be current); once per device, at context creation
+int subtract_scratch_init(argus_ctx *ctx);
 int launch_detect(argus_ctx *ctx, argus_dims d, const float *diff, const float *dvar,
                   const uint8_t *dmask, float thr, const float *psf, int r, float *snr,
                   uint8_t *det, argus_candidate *cands, int32_t cap, int32_t *n_cands);

@@ -9,7 +9,15 @@
 // pixels, the reference and variance windows of a kernel row sit in
 // registers, and each tap costs 5 VALU ops per pixel (2 for a constant
 // kernel).  Workgroups are 128x16 output pixels with an h-pixel halo in LDS.
+#include <mutex>
+
 #include "internal.h"
+
+// Block partials of argus_subtract_noalloc: a fixed device array, so that
+// entry point allocates nothing.  Host code never passes the name itself to a
+// kernel (it stands for a host-side shadow); it passes the device address
+// fetched once per device by subtract_scratch_init.
+static __device__ __align__(256) double scratch[(size_t)ARGUS_NOALLOC_MAX_BLOCKS * 4];
 
 namespace {
 
@@ -368,12 +376,31 @@ inline bool aligned(const void *p, size_t al) { return ((uintptr_t)p % al) == 0;
 
 }  // namespace
 
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[ARGUS_MAX_DEVICES] = {};
+}  // namespace
+
+int subtract_scratch_init(argus_ctx *ctx) {
+    if (ctx->device < 0 || ctx->device >= ARGUS_MAX_DEVICES)
+        return argus_fail(ctx, ARGUS_EINVAL, "device %d beyond the scratch table", ctx->device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[ctx->device]) return ARGUS_OK;
+    // the caller made ctx->device current; each device has its own copy
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return argus_fail(ctx, ARGUS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[ctx->device] = (double *)p;
+    return ARGUS_OK;
+}
+
 int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
                     const float *stamps, const float *bg, const float *ref,
                     const float *ref_var, const uint8_t *ref_mask, const float *sci,
                     const float *sci_var, const uint8_t *sci_mask, float *diff, float *diff_var,
                     uint8_t *diff_mask, double *chi2, int64_t *n_chi2, double *sum_wd,
-                    double *sum_w) {
+                    double *sum_w, bool noalloc) {
     SubArgs a;
     a.stamps = stamps; a.bg = bg; a.ref = ref; a.rvar = ref_var; a.sci = sci; a.svar = sci_var;
     a.rmask = ref_mask; a.smask = sci_mask; a.diff = diff; a.dvar = diff_var; a.dmask = diff_mask;
@@ -391,17 +418,28 @@ int launch_subtract(argus_ctx *ctx, argus_dims d, const argus_kernel_spec *spec,
     const int n_solves = a.RX * a.RY;
     const int per_solve = a.bpx * a.bpy;
     const int n_blocks = n_solves * per_solve;
-    int rc = argus_ws_reserve(ctx, (size_t)n_blocks * 4 * sizeof(double) + 256);
-    if (rc) return rc;
-    a.partials = (double *)ctx->ws;
-    argus_time_begin(ctx);
+    int rc;
+    if (noalloc) {
+        if (n_blocks > ARGUS_NOALLOC_MAX_BLOCKS)
+            return argus_fail(ctx, ARGUS_ESHAPE,
+                              "argus_subtract_noalloc: %d blocks of 128x16 pixels exceed the "
+                              "scratch maximum of %d", n_blocks, ARGUS_NOALLOC_MAX_BLOCKS);
+        double *p = (ctx->device >= 0 && ctx->device < ARGUS_MAX_DEVICES)
+                        ? g_scratch_ptr[ctx->device] : nullptr;
+        if (!p) return argus_fail(ctx, ARGUS_EHIP, "scratch address not initialised");
+        a.partials = p;
+    } else {
+        if ((rc = argus_ws_reserve(ctx, (size_t)n_blocks * 4 * sizeof(double) + 256))) return rc;
+        a.partials = (double *)ctx->ws;
+    }
+    if (!noalloc) argus_time_begin(ctx);
     switch (a.D) {
         case 0: rc = sub_dispatch_h<0>(ctx, a, spec->half_width, n_blocks); break;
         case 1: rc = sub_dispatch_h<1>(ctx, a, spec->half_width, n_blocks); break;
         default: rc = sub_dispatch_h<2>(ctx, a, spec->half_width, n_blocks); break;
     }
     if (rc) return rc;
-    argus_time_end(ctx, "subtract");
+    if (!noalloc) argus_time_end(ctx, "subtract");
     if (chi2 || n_chi2 || sum_wd || sum_w) {
         hipLaunchKernelGGL(chi2_reduce_kernel, dim3(n_solves), dim3(256), 0, ctx->stream,
                            (const double *)a.partials, per_solve, chi2, n_chi2, sum_wd, sum_w);
