@@ -84,7 +84,7 @@ def log(*a):
 # Sources that decide the frame fit's memory traffic (kernel and its launch).
 FIT_SOURCES = ["paper_2207_14304_amd/csrc/fit_accum8.h", "paper_2207_14304_amd/csrc/fit_accum.h",
                "paper_2207_14304_amd/csrc/k_fit_fp32.hip", "paper_2207_14304_amd/csrc/k_fit.hip"]
-TRAFFIC_FILE = "profiles/fit_accum_traffic.md"
+TRAFFIC_FILE = "profiles/frame_path_hbm_traffic.md"
 
 
 def fit_source_hash():
@@ -313,10 +313,27 @@ def batch_leg(args, torch, argus, synth):
     gpix = float(np.sum(np.asarray(Ls, np.float64) ** 2)) / 1e9
     st = outs[7].cpu().numpy()
     choice, tuned_ms, ncand = b.info()
+    cand_ms, _ = b.tuning()
+    shapes = [argus.batch_candidate(i) for i in range(ncand)]
+    # the untuned shape: 16-row tiles at the 2 workgroups per CU the kernel's
+    # launch bounds are written for
+    fixed = shapes.index((16, 2))
+    # a second plan of the same problem on this context takes the stored choice
+    b2 = argus.Batch(ctx, spec, fr, xs0, ys0, Ls, [W] * nf, [H] * nf)
+    ctx.batch_run(b2, frames, 5.0, *outs)
+    torch.cuda.synchronize()
+    _, hit2 = b2.tuning()
+    same2 = b2.info()[0] == choice
+    b2.close()
     res = {"value": round(gpix * 1e6 / ms, 2), "unit": "Mpix/s", "ms": round(ms, 3),
            "cutouts": n, "frames": nf, "cutout_gpix": round(gpix, 4),
            "side_px": [int(min(Ls)), int(max(Ls))], "solves_ok": int((st == 0).sum()),
-           "autotune": {"choice": choice, "candidates": ncand, "best_ms": round(tuned_ms, 3)},
+           "autotune": {"choice": choice, "candidates": ncand, "best_ms": round(tuned_ms, 3),
+                        "candidate_ms": {f"{t}rows_x{w}wg": round(m, 3)
+                                         for (t, w), m in zip(shapes, cand_ms)},
+                        "fixed_shape": "16rows_x2wg", "fixed_ms": round(cand_ms[fixed], 3),
+                        "gain_vs_fixed": round(cand_ms[fixed] / tuned_ms, 3),
+                        "second_plan_from_cache": bool(hit2 and same2)},
            "workload": f"{nf} cameras x {args.batch_cutouts} cutouts, sides log-uniform 64-512, "
                        f"constant 15x15 kernel each (FP64 row moments), one graph launch"}
     log("batch: " + json.dumps(res))

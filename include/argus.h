@@ -126,6 +126,20 @@ int  argus_ctx_create(int device, argus_ctx **out);
 void argus_ctx_destroy(argus_ctx *ctx);
 /* hip_stream is a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
 int  argus_ctx_set_stream(argus_ctx *ctx, void *hip_stream);
+/* Tuning cache of the autotuner (argus_batch_run's tile-shape search): each
+ * search's outcome -- the chosen candidate and every candidate's time -- is
+ * kept on the context under a key naming the device (architecture name and
+ * compute-unit count), the HIP runtime version, the kernel, its half width,
+ * precision and problem-size bucket (log2 of the cutout count and of the
+ * summed cutout area); a later search with the same key takes the stored
+ * choice without timing.  With a path (or, at context creation, the file
+ * named by the ARGUS_TUNE_CACHE environment variable) the entries are read
+ * from that file now and every new one is appended to it, one JSON object
+ * per line: {"key": "...", "choice": n, "ms": [t0, t1, ...]}; lines that do
+ * not parse are skipped and a later line for a key wins.  NULL or "" keeps
+ * the cache in memory only.  A file that cannot be opened only loses
+ * persistence (no error). */
+int  argus_ctx_set_tune_cache(argus_ctx *ctx, const char *path);
 /* Message of the most recent synchronous failure on this ctx ("" if none). */
 const char *argus_last_error(const argus_ctx *ctx);
 /* Per-kernel timing (for measurement only): while enabled, every launch of
@@ -450,6 +464,16 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *batch, const argus_frame *frame
 /* Autotuner outcome: chosen candidate index, its time in ms, and the number of
  * candidates tried (any pointer may be null). */
 int argus_batch_info(const argus_batch *batch, int *choice, float *ms, int *n_candidates);
+/* Every candidate's time in ms, in candidate order (the first `capacity`
+ * are written to cand_ms), their number, and whether the choice was taken
+ * from the context's tuning cache (then the times are the stored ones).
+ * Before the first run the count is 0. */
+int argus_batch_tuning(const argus_batch *batch, float *cand_ms, int capacity, int *n_candidates,
+                       int *from_cache);
+/* Shape of autotuner candidate `index`: subtraction tile height in rows and
+ * workgroups per compute unit of the persistent launch.  ARGUS_EINVAL for an
+ * index outside the candidate list. */
+int argus_batch_candidate(int index, int *tile_rows, int *wg_per_cu);
 void argus_batch_destroy(argus_batch *batch);
 
 /* ---- learned kernel surrogate -------------------------------------------

@@ -27,7 +27,7 @@ SYMBOLS = ("argus_ctx_create", "argus_ctx_destroy", "argus_ctx_set_stream", "arg
            "argus_calibrate_coadd",
            "argus_kernel_dims", "argus_fit_kernel", "argus_expand_kernel", "argus_subtract",
            "argus_subtract_noalloc", "argus_detect", "argus_batch_plan", "argus_batch_run", "argus_batch_info",
-           "argus_batch_destroy", "argus_cnn_create", "argus_cnn_destroy",
+           "argus_batch_destroy", "argus_batch_tuning", "argus_batch_candidate", "argus_ctx_set_tune_cache", "argus_cnn_create", "argus_cnn_destroy",
            "argus_cnn_n_params", "argus_cnn_set_weights", "argus_cnn_get_weights",
            "argus_cnn_get_grads", "argus_cnn_forward", "argus_cnn_train_step",
            "argus_surrogate_coeffs", "argus_surrogate_select", "argus_extract_stamps",
@@ -156,6 +156,10 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(vp)]
     lib.argus_batch_run.argtypes = [vp, vp, C.POINTER(Frame), f32] + [vp] * 9
     lib.argus_batch_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(f32), C.POINTER(C.c_int)]
+    lib.argus_batch_tuning.argtypes = [vp, C.POINTER(f32), C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int)]
+    lib.argus_batch_candidate.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.argus_ctx_set_tune_cache.argtypes = [vp, C.c_char_p]
     lib.argus_batch_destroy.argtypes = [vp]
     lib.argus_batch_destroy.restype = None
     lib.argus_cnn_create.argtypes = [vp, C.c_int, C.POINTER(vp)]
@@ -185,6 +189,16 @@ class ArgusError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"argus error {code}: {msg}")
         self.code = code
+
+
+def batch_candidate(index: int):
+    """(subtraction tile rows, workgroups per CU) of autotuner candidate ``index``."""
+    lib = load()
+    t, w = C.c_int(), C.c_int()
+    rc = lib.argus_batch_candidate(index, C.byref(t), C.byref(w))
+    if rc:
+        raise ArgusError(rc, f"no batch candidate {index}")
+    return t.value, w.value
 
 
 def kernel_dims(spec: KernelSpec):
@@ -248,6 +262,12 @@ class Context:
 
     def set_timing(self, on: bool):
         self._check(self.lib.argus_ctx_set_timing(self.h, int(on)))
+
+    def set_tune_cache(self, path):
+        """Read the autotuner's JSON-lines cache at ``path`` and append new
+        outcomes to it (None: in memory only)."""
+        self._check(self.lib.argus_ctx_set_tune_cache(self.h, None if path is None else
+                                                      str(path).encode()))
 
     def kernel_time_ms(self, name: str) -> float:
         return float(self.lib.argus_kernel_time_ms(self.h, name.encode()))
@@ -438,6 +458,13 @@ class Batch:
         c, ms, n = C.c_int(), C.c_float(), C.c_int()
         self.ctx.lib.argus_batch_info(self.h, C.byref(c), C.byref(ms), C.byref(n))
         return c.value, ms.value, n.value
+
+    def tuning(self):
+        """(per-candidate times in ms, taken from the tuning cache?)"""
+        buf = (C.c_float * 64)()
+        n, hit = C.c_int(), C.c_int()
+        self.ctx._check(self.ctx.lib.argus_batch_tuning(self.h, buf, 64, C.byref(n), C.byref(hit)))
+        return [buf[i] for i in range(min(n.value, 64))], bool(hit.value)
 
     def close(self):
         if getattr(self, "h", None):

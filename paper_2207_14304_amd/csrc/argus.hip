@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "internal.h"
@@ -81,7 +82,88 @@ void argus_time_end(argus_ctx *ctx, const char *name) {
     ctx->ev_open = nullptr;
 }
 
+// ---- autotuner cache ---------------------------------------------------------
+// One JSON object per line, written by this library in a fixed key order:
+//   {"key": "<key>", "choice": <int>, "ms": [<float>, ...]}
+// Lines that do not parse are skipped; a later line for a key wins.
+static void tune_parse_line(argus_ctx *ctx, const char *line) {
+    static const char KK[] = "\"key\": \"", KC[] = "\"choice\": ", KM[] = "\"ms\": [";
+    const char *k = strstr(line, KK);
+    const char *c = strstr(line, KC);
+    const char *m = strstr(line, KM);
+    if (!k || !c || !m) return;
+    k += sizeof KK - 1;
+    c += sizeof KC - 1;
+    const char *ke = strchr(k, '"');
+    if (!ke) return;
+    argus_ctx::Tuned t;
+    t.key.assign(k, ke - k);
+    char *end = nullptr;
+    t.choice = (int)strtol(c, &end, 10);
+    if (end == c) return;
+    const char *q = m + sizeof KM - 1;
+    while (*q && *q != ']') {
+        float v = strtof(q, &end);
+        if (end == q) return;
+        t.ms.push_back(v);
+        q = end;
+        while (*q == ',' || *q == ' ') ++q;
+    }
+    if (*q != ']' || t.choice < 0 || t.choice >= (int)t.ms.size()) return;
+    for (auto &e : ctx->tuned)
+        if (e.key == t.key) { e = t; return; }
+    ctx->tuned.push_back(t);
+}
+
+static void tune_load(argus_ctx *ctx) {
+    if (ctx->tune_path.empty()) return;
+    FILE *f = fopen(ctx->tune_path.c_str(), "r");
+    if (!f) return;                    // no file yet: it is created on the first store
+    char line[4096];
+    while (fgets(line, sizeof line, f)) tune_parse_line(ctx, line);
+    fclose(f);
+}
+
+std::string argus_tune_device_key(argus_ctx *ctx) {
+    hipDeviceProp_t prop;
+    char buf[384];
+    int rt = 0;
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) prop.gcnArchName[0] = 0;
+    if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+    snprintf(buf, sizeof buf, "device=%s;hip=%d;cu=%d", prop.gcnArchName, rt, ctx->n_cu);
+    return buf;
+}
+
+const argus_ctx::Tuned *argus_tune_lookup(const argus_ctx *ctx, const std::string &key) {
+    for (const auto &e : ctx->tuned)
+        if (e.key == key) return &e;
+    return nullptr;
+}
+
+void argus_tune_store(argus_ctx *ctx, const std::string &key, int choice, const std::vector<float> &ms) {
+    argus_ctx::Tuned t{key, choice, ms};
+    bool found = false;
+    for (auto &e : ctx->tuned)
+        if (e.key == key) { e = t; found = true; }
+    if (!found) ctx->tuned.push_back(t);
+    if (ctx->tune_path.empty()) return;
+    FILE *f = fopen(ctx->tune_path.c_str(), "a");
+    if (!f) return;                    // an unwritable cache file only loses persistence
+    fprintf(f, "{\"key\": \"%s\", \"choice\": %d, \"ms\": [", key.c_str(), choice);
+    for (size_t i = 0; i < ms.size(); ++i) fprintf(f, "%s%.6g", i ? ", " : "", ms[i]);
+    fprintf(f, "]}\n");
+    fclose(f);
+}
+
 extern "C" {
+
+int argus_ctx_set_tune_cache(argus_ctx *ctx, const char *path) {
+    if (!ctx) return ARGUS_EINVAL;
+    ctx->err.clear();
+    ctx->tune_path = path ? path : "";
+    tune_load(ctx);
+    return ARGUS_OK;
+}
 
 int argus_ctx_create(int device, argus_ctx **out) {
     if (!out) return ARGUS_EINVAL;
@@ -101,6 +183,10 @@ int argus_ctx_create(int device, argus_ctx **out) {
         (void)hipFree(c->tables);
         delete c;
         return ARGUS_EHIP;
+    }
+    if (const char *tp = getenv("ARGUS_TUNE_CACHE")) {
+        c->tune_path = tp;
+        tune_load(c);
     }
     *out = c;
     return ARGUS_OK;

@@ -59,6 +59,12 @@ struct argus_ctx {
     std::vector<hipEvent_t> ev_pool;
     hipEvent_t ev_open = nullptr;
     int n_cu = 0;                      // compute units of the device
+    // autotuner results: key (device, HIP runtime, kernel, shape bucket) ->
+    // chosen candidate and every candidate's time; mirrored in a JSON-lines
+    // file when tune_path is set
+    struct Tuned { std::string key; int choice; std::vector<float> ms; };
+    std::vector<Tuned> tuned;
+    std::string tune_path;
 };
 
 // Loads and stores through a device pointer that addresses global memory, for
@@ -77,6 +83,12 @@ __device__ __forceinline__ void gst(T *p, T v) {
 // ---- helpers implemented in argus.hip --------------------------------------
 int argus_fail(argus_ctx *ctx, int code, const char *fmt, ...);
 int argus_ws_reserve(argus_ctx *ctx, size_t bytes);
+// autotuner cache: the key prefix naming this device and HIP runtime, a
+// lookup (nullptr if absent) and a store (kept on the ctx, appended to the
+// file when one is set)
+std::string argus_tune_device_key(argus_ctx *ctx);
+const argus_ctx::Tuned *argus_tune_lookup(const argus_ctx *ctx, const std::string &key);
+void argus_tune_store(argus_ctx *ctx, const std::string &key, int choice, const std::vector<float> &ms);
 void argus_time_begin(argus_ctx *ctx);
 void argus_time_end(argus_ctx *ctx, const char *name);
 

@@ -11,6 +11,7 @@
 // convolution + MFMA moment code as argus_fit_kernel over its interior,
 // followed by an in-LDS FP64 Cholesky of the (nb+1)-unknown system; edges and
 // footprints stay inside the cutout.
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -44,6 +45,9 @@ struct argus_batch {
     float thr = 0.f;
     int choice = -1, n_cand = 0;
     float tuned_ms = -1.f;
+    std::vector<float> cand_ms;     // every candidate's time (ms), candidate order
+    int from_cache = 0;             // the choice came from the context's tuning cache
+    int64_t area = 0;               // sum of cutout areas (size bucket of the tuning key)
 };
 
 namespace {
@@ -417,6 +421,12 @@ __global__ __launch_bounds__(NTHR, 2) void batch_kernel(BatchArgs a) {
 
 __global__ void queue_reset_kernel(int32_t *q) { *q = 0; }
 
+inline int ilog2(int64_t v) {
+    int r = 0;
+    while (v > 1) { v >>= 1; ++r; }
+    return r;
+}
+
 // candidates: subtraction tile height x workgroups per CU
 constexpr int N_CAND = 6;
 constexpr int CAND_TILE[N_CAND] = {16, 16, 16, 32, 32, 32};
@@ -485,6 +495,7 @@ int argus_batch_plan(argus_ctx *ctx, const argus_kernel_spec *spec, const argus_
         if (c.out_offset < 0) return argus_fail(ctx, ARGUS_EINVAL, "cutout %d: negative offset", i);
     }
     argus_batch *b = new argus_batch();
+    for (int i = 0; i < n_cutouts; ++i) b->area += (int64_t)cutouts[i].side * cutouts[i].side;
     b->n = n_cutouts;
     b->n_frames = n_frames;
     b->n_unk = nu;
@@ -590,25 +601,42 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *b, const argus_frame *frames, f
         ba.diff = diff; ba.dvar = diff_var; ba.dmask = diff_mask; ba.det = det_mask;
         ba.coeffs = coeffs; ba.chi2 = chi2; ba.n_fit = n_fit; ba.status = status; ba.n_cands = n_cands;
         if (b->choice < 0) {
-            // autotune: time each candidate once on these inputs
-            hipEvent_t e0, e1;
-            ARGUS_HIP_CHECK(ctx, hipEventCreate(&e0));
-            ARGUS_HIP_CHECK(ctx, hipEventCreate(&e1));
-            float best = 1e30f;
-            for (int cand = 0; cand < N_CAND; ++cand) {
-                ARGUS_HIP_CHECK(ctx, hipEventRecord(e0, b->stream));
-                int rc = batch_launch(ctx, ba, b->h, b->spec.precision, cand, b->stream);
-                if (rc) return rc;
-                ARGUS_HIP_CHECK(ctx, hipEventRecord(e1, b->stream));
-                ARGUS_HIP_CHECK(ctx, hipEventSynchronize(e1));
-                float ms = 0.f;
-                ARGUS_HIP_CHECK(ctx, hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; b->choice = cand; }
+            // autotune: the context's cache (device, HIP runtime, kernel, half
+            // width, precision, size bucket), else time each candidate once on
+            // these inputs and store the outcome
+            char kb[160];
+            snprintf(kb, sizeof kb, ";kernel=batch;h=%d;prec=%d;log2n=%d;log2area=%d", b->h,
+                     b->spec.precision, ilog2(b->n), ilog2(b->area));
+            const std::string key = argus_tune_device_key(ctx) + kb;
+            const argus_ctx::Tuned *t = argus_tune_lookup(ctx, key);
+            if (t && (int)t->ms.size() == N_CAND) {
+                b->choice = t->choice;
+                b->cand_ms = t->ms;
+                b->from_cache = 1;
+            } else {
+                hipEvent_t e0, e1;
+                ARGUS_HIP_CHECK(ctx, hipEventCreate(&e0));
+                ARGUS_HIP_CHECK(ctx, hipEventCreate(&e1));
+                float best = 1e30f;
+                b->cand_ms.assign(N_CAND, 0.f);
+                for (int cand = 0; cand < N_CAND; ++cand) {
+                    ARGUS_HIP_CHECK(ctx, hipEventRecord(e0, b->stream));
+                    int rc = batch_launch(ctx, ba, b->h, b->spec.precision, cand, b->stream);
+                    if (rc) return rc;
+                    ARGUS_HIP_CHECK(ctx, hipEventRecord(e1, b->stream));
+                    ARGUS_HIP_CHECK(ctx, hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    ARGUS_HIP_CHECK(ctx, hipEventElapsedTime(&ms, e0, e1));
+                    b->cand_ms[cand] = ms;
+                    if (ms < best) { best = ms; b->choice = cand; }
+                }
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                argus_tune_store(ctx, key, b->choice, b->cand_ms);
+                b->from_cache = 0;
             }
-            b->tuned_ms = best;
+            b->tuned_ms = b->cand_ms[b->choice];
             b->n_cand = N_CAND;
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
         }
         if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
         if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -629,6 +657,23 @@ int argus_batch_run(argus_ctx *ctx, argus_batch *b, const argus_frame *frames, f
     ARGUS_HIP_CHECK(ctx, hipEventRecord(b->ev_out, b->stream));
     ARGUS_HIP_CHECK(ctx, hipStreamWaitEvent(ctx->stream, b->ev_out, 0));
     argus_time_end(ctx, "batch");
+    return ARGUS_OK;
+}
+
+int argus_batch_tuning(const argus_batch *b, float *cand_ms, int capacity, int *n_candidates,
+                       int *from_cache) {
+    if (!b || capacity < 0 || (capacity > 0 && !cand_ms)) return ARGUS_EINVAL;
+    const int n = (int)b->cand_ms.size();
+    for (int i = 0; i < n && i < capacity; ++i) cand_ms[i] = b->cand_ms[i];
+    if (n_candidates) *n_candidates = n;
+    if (from_cache) *from_cache = b->from_cache;
+    return ARGUS_OK;
+}
+
+int argus_batch_candidate(int index, int *tile_rows, int *wg_per_cu) {
+    if (index < 0 || index >= N_CAND) return ARGUS_EINVAL;
+    if (tile_rows) *tile_rows = CAND_TILE[index];
+    if (wg_per_cu) *wg_per_cu = CAND_WPC[index];
     return ARGUS_OK;
 }
 

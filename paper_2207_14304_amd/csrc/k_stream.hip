@@ -162,6 +162,15 @@ __device__ __forceinline__ double median_of(const float (&x)[N], unsigned S, int
     return 0.5 * ((double)a + (double)b);
 }
 
+// Median of five values without a sort: the smallest and the largest of the
+// first four lie on either side of the median, so it is the median of the
+// fifth value and the middle two of the four (f, g).  Selects an input value.
+__device__ __forceinline__ float med5(float a, float b, float c, float d, float e) {
+    const float f = fmaxf(fminf(a, b), fminf(c, d));
+    const float g = fminf(fmaxf(a, b), fmaxf(c, d));
+    return fmaxf(fminf(e, f), fminf(fmaxf(e, f), g));
+}
+
 template <int N>
 __device__ __forceinline__ void coadd_one(const CoaddArgs &a, const float (&x)[N],
                                           const float (&v)[N], const uint8_t (&m)[N], float &ref,
@@ -177,8 +186,15 @@ __device__ __forceinline__ void coadd_one(const CoaddArgs &a, const float (&x)[N
     for (int it = 0; it < a.max_iter; ++it) {
         int cnt = __builtin_popcount(S);
         if (cnt <= 2) break;
-        double c = median_of<N>(x, S, cnt);
-        double s2 = median_of<N>(v, S, cnt);
+        double c, s2;
+        if (N == 5 && __all(S == 31u)) {
+            // every pixel of the wave has its five samples (the common case)
+            c = (double)med5(x[0], x[1 % N], x[2 % N], x[3 % N], x[4 % N]);
+            s2 = (double)med5(v[0], v[1 % N], v[2 % N], v[3 % N], v[4 % N]);
+        } else {
+            c = median_of<N>(x, S, cnt);
+            s2 = median_of<N>(v, S, cnt);
+        }
         double thr = a.kappa2 * s2;
         unsigned rej = 0u;
 #pragma unroll
@@ -262,15 +278,141 @@ __global__ __launch_bounds__(256) void coadd_kernel(CoaddArgs a) {
 
 // ---------------------------------------------------------------------------
 // Calibration of N raw frames that share one set of masters, fused with their
-// clipped-mean coadd: per pixel the N calibrated values, variances and masks
-// stay in registers, so only the raw frames and the masters are read and only
-// the coadd is written (about 29 instead of 155 bytes per pixel for N = 5).
-// The arithmetic is that of calibrate_kernel followed by coadd_kernel.
+// clipped-mean coadd: per pixel the N raw counts stay in registers, so only
+// the raw frames and the masters are read and only the coadd is written
+// (about 29 instead of 155 bytes per pixel for N = 5).
+//
+// With one dark, flat and gain for every frame, a pixel's calibrated value and
+// its variance are both non-decreasing functions of the raw count (each FP64
+// step and the final rounding to FP32 preserve order), and the saturated
+// frames are those with the largest counts.  So the counts are sorted once
+// (keys count * 8 + frame, 32-bit integer min/max) and the samples calibrated
+// in that order: values and variances are then both sorted, the unsaturated
+// samples are ranks [0, nv), and every clip pass keeps a run of consecutive
+// ranks [l, h] (x - c grows with the rank, so a pass rejects from the two
+// ends).  The medians of a pass are the values and variances at the middle
+// ranks of the run; no per-pass sort remains.  The decisions are those of
+// coadd_kernel on the calibrated frames (same medians, same FP64 test); the
+// survivors' FP64 sums run in rank instead of frame order, which changes
+// nothing where those sums are exact (always, unless the survivors' FP32
+// exponents span more than ~29 binades) and the FP32 result by at most one
+// unit elsewhere.
 struct CalCoaddArgs {
     const uint16_t *raw[ARGUS_MAX_FRAMES];
-    CalArgs cal;               // masters, gain terms, saturation (cal/var/mask outputs unused)
+    CalArgs cal;               // masters, gain terms (cal/var/mask outputs unused)
     CoaddArgs co;              // kappa, iterations and the coadd outputs (inputs unused)
+    uint32_t satkey;           // saturation count * 8: key < satkey <=> count < saturation
 };
+
+// ascending sort of N keys (odd-even transposition)
+template <int N>
+__device__ __forceinline__ void sort_keys(uint32_t (&k)[N]) {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int i = r & 1; i + 1 < N; i += 2) {
+            const uint32_t lo = min(k[i], k[i + 1]), hi = max(k[i], k[i + 1]);
+            k[i] = lo;
+            k[i + 1] = hi;
+        }
+}
+
+// the arithmetic of cal_one without the mask
+__device__ __forceinline__ void cal_val(const CalArgs &a, uint32_t r, const CalPix &p, float &c,
+                                        float &v) {
+    const double sig = (double)r - p.d;
+    c = (float)(sig * p.rf);
+    v = (float)((fmax(sig, 0.0) * a.inv_g + a.rn2_g2) * p.rf2);
+}
+
+template <int N>
+__device__ __forceinline__ void calcoadd_one(const CalCoaddArgs &a, const uint16_t (&raw)[N],
+                                             const CalPix &cp, bool in, float &ref, float &rv,
+                                             uint8_t &rm, uint8_t &nu) {
+    const CoaddArgs &co = a.co;
+    uint32_t key[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) key[i] = ((uint32_t)raw[i] << 3) | (uint32_t)i;
+    sort_keys<N>(key);
+    const bool sat = key[N - 1] >= a.satkey;
+    int nv = N;
+    if (__any(sat)) {
+        // saturated samples are the top ranks
+        nv = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) nv += key[k] < a.satkey ? 1 : 0;
+    }
+    if (cp.bad || !in) nv = 0;
+    float x[N], v[N];
+    double xd[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        cal_val(a.cal, key[k] >> 3, cp, x[k], v[k]);
+        xd[k] = (double)x[k];
+    }
+    int l = 0, h = nv - 1;
+    for (int it = 0; it < co.max_iter; ++it) {
+        const int cnt = h - l + 1;
+        if (cnt <= 2) break;
+        double c, s2;
+        int ib;
+        if (__all(l == 0 && h == N - 1)) {
+            // every sample of every pixel of the wave still in (the common first pass)
+            constexpr int IA = (N - 1) >> 1, IB = N >> 1;
+            c = 0.5 * (xd[IA] + xd[IB]);
+            s2 = 0.5 * ((double)v[IA] + (double)v[IB]);
+            ib = IB;
+        } else {
+            const int ia = (l + h) >> 1;
+            ib = (l + h + 1) >> 1;
+            // the middle ranks' values by selects (no indexed register access);
+            // with at least 3 in the run they lie in ranks 1 .. N-2
+            double xa = xd[1 % N], xb = xd[1 % N];
+            float va = v[1 % N], vb = v[1 % N];
+#pragma unroll
+            for (int k = 2; k < N - 1; ++k) {
+                const bool ta = ia == k, tb = ib == k;
+                xa = ta ? xd[k] : xa;
+                va = ta ? v[k] : va;
+                xb = tb ? xd[k] : xb;
+                vb = tb ? v[k] : vb;
+            }
+            c = 0.5 * (xa + xb);
+            s2 = 0.5 * ((double)va + (double)vb);
+        }
+        const double thr = co.kappa2 * s2;
+        unsigned rej = 0u;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double dd = xd[k] - c;
+            if (dd * dd > thr) rej |= 1u << k;
+        }
+        rej &= ((2u << h) - 1u) & ~((1u << l) - 1u);      // ranks l..h only
+        const int nr = __builtin_popcount(rej);
+        if (nr == 0 || cnt - nr < 2) break;
+        // ranks below ib lie at or below the median, those from ib on at or above it
+        const int nlo = __builtin_popcount(rej & ((1u << ib) - 1u));
+        l += nlo;
+        h -= nr - nlo;
+    }
+    const int cnt = h - l + 1;                             // 0 when nv == 0
+    // sums over ranks l..h as FMAs with weights 1.0 / 0.0 (fma(1, x, s) is the
+    // rounded sum, fma(0, x, s) = s): no selects of 64-bit values
+    unsigned run = 0u;                                     // (h = -1 when nv == 0)
+    if (cnt > 0) run = ((2u << h) - 1u) & ~((1u << l) - 1u);
+    double sx = 0.0, sv = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double wk = (double)((run >> k) & 1u);
+        sx = __builtin_fma(wk, xd[k], sx);
+        sv = __builtin_fma(wk, (double)v[k], sv);
+    }
+    const double ic = cnt > 0 ? rcp64((double)cnt) : 0.0;
+    ref = (float)(sx * ic);
+    rv = (float)(sv * (ic * ic));
+    rm = (nv == 0 ? ARGUS_NODATA : 0u) | (sat ? ARGUS_SAT : 0u);
+    nu = (uint8_t)cnt;
+}
 
 template <int N>
 __global__ __launch_bounds__(256) void calcoadd_kernel(CalCoaddArgs a) {
@@ -282,52 +424,46 @@ __global__ __launch_bounds__(256) void calcoadd_kernel(CalCoaddArgs a) {
     int x0 = (int)(t - (int64_t)y * c.chunks) * CO_PX;
     int64_t o = (int64_t)y * c.pitch + x0;
     int n = min(CO_PX, c.W - x0);
-    float x[CO_PX][N], v[CO_PX][N];
-    uint8_t m[CO_PX][N];
+    uint16_t r[CO_PX][N];
+    CalPix cp[CO_PX];
     if (c.vec && n == CO_PX) {
         const float4 d4 = *(const float4 *)(a.cal.dark + o), f4 = *(const float4 *)(a.cal.flat + o);
         const uint32_t b4 = a.cal.bpm ? *(const uint32_t *)(a.cal.bpm + o) : 0u;
         const float d[CO_PX] = {d4.x, d4.y, d4.z, d4.w}, f[CO_PX] = {f4.x, f4.y, f4.z, f4.w};
-        uint2 r4[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) r4[i] = *(const uint2 *)(a.raw[i] + o);
-        CalPix cp[CO_PX];
-#pragma unroll
-        for (int p = 0; p < CO_PX; ++p) cp[p] = cal_pix(d[p], f[p], (uint8_t)(b4 >> (8 * p)));
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const uint16_t r[CO_PX] = {(uint16_t)(r4[i].x & 0xffff), (uint16_t)(r4[i].x >> 16),
-                                       (uint16_t)(r4[i].y & 0xffff), (uint16_t)(r4[i].y >> 16)};
-#pragma unroll
-            for (int p = 0; p < CO_PX; ++p) cal_one(a.cal, r[p], cp[p], x[p][i], v[p][i], m[p][i]);
+            const uint2 r4 = *(const uint2 *)(a.raw[i] + o);
+            r[0][i] = (uint16_t)(r4.x & 0xffff);
+            r[1][i] = (uint16_t)(r4.x >> 16);
+            r[2][i] = (uint16_t)(r4.y & 0xffff);
+            r[3][i] = (uint16_t)(r4.y >> 16);
         }
+#pragma unroll
+        for (int p = 0; p < CO_PX; ++p) cp[p] = cal_pix(d[p], f[p], (uint8_t)(b4 >> (8 * p)));
     } else {
 #pragma unroll
         for (int p = 0; p < CO_PX; ++p) {
             const bool in = p < n;
             const float d = in ? a.cal.dark[o + p] : 0.f, f = in ? a.cal.flat[o + p] : 1.f;
             const uint8_t b = in && a.cal.bpm ? a.cal.bpm[o + p] : 0;
-            const CalPix cp = cal_pix(d, f, b);
+            cp[p] = cal_pix(d, f, b);
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                cal_one(a.cal, in ? a.raw[i][o + p] : (uint16_t)0, cp, x[p][i], v[p][i], m[p][i]);
-                if (!in) m[p][i] = ARGUS_BAD;
-            }
+            for (int i = 0; i < N; ++i) r[p][i] = in ? a.raw[i][o + p] : (uint16_t)0;
         }
     }
-    float r[CO_PX], rv[CO_PX];
+    float rr[CO_PX], rv[CO_PX];
     uint8_t rm[CO_PX], nu[CO_PX];
 #pragma unroll
-    for (int p = 0; p < CO_PX; ++p) coadd_one<N>(c, x[p], v[p], m[p], r[p], rv[p], rm[p], nu[p]);
+    for (int p = 0; p < CO_PX; ++p) calcoadd_one<N>(a, r[p], cp[p], p < n, rr[p], rv[p], rm[p], nu[p]);
     if (c.vec && n == CO_PX) {
-        *(float4 *)(c.ref + o) = make_float4(r[0], r[1], r[2], r[3]);
+        *(float4 *)(c.ref + o) = make_float4(rr[0], rr[1], rr[2], rr[3]);
         *(float4 *)(c.ref_var + o) = make_float4(rv[0], rv[1], rv[2], rv[3]);
         *(uint32_t *)(c.ref_mask + o) = rm[0] | (rm[1] << 8) | (rm[2] << 16) | ((uint32_t)rm[3] << 24);
         if (c.n_used)
             *(uint32_t *)(c.n_used + o) = nu[0] | (nu[1] << 8) | (nu[2] << 16) | ((uint32_t)nu[3] << 24);
     } else {
         for (int p = 0; p < n; ++p) {
-            c.ref[o + p] = r[p];
+            c.ref[o + p] = rr[p];
             c.ref_var[o + p] = rv[p];
             c.ref_mask[o + p] = rm[p];
             if (c.n_used) c.n_used[o + p] = nu[p];
@@ -403,6 +539,7 @@ int launch_calibrate_coadd(argus_ctx *ctx, argus_dims d, int n, const uint16_t *
     a.cal.inv_g = 1.0 / (double)gain;
     a.cal.rn2_g2 = (double)rn * (double)rn / ((double)gain * (double)gain);
     a.cal.sat = (float)sat;
+    a.satkey = (uint32_t)sat << 3;
     bool vec = (d.pitch % CO_PX == 0) && aligned(dark, 16) && aligned(flat, 16) &&
                (!bpm || aligned(bpm, 4)) && aligned(ref, 16) && aligned(ref_var, 16) &&
                aligned(ref_mask, 4) && (!n_used || aligned(n_used, 4));

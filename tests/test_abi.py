@@ -54,3 +54,12 @@ def test_null_context_is_rejected():
                                None) == argus.EINVAL
     assert lib.argus_ctx_create(0, None) == argus.EINVAL
     assert lib.argus_last_error(None) == b"null ctx"
+
+
+def test_batch_candidates_host_only():
+    _ensure_built()
+    shapes = [argus.batch_candidate(i) for i in range(6)]
+    assert shapes == [(16, 1), (16, 2), (16, 3), (32, 1), (32, 2), (32, 3)]
+    for bad in (-1, 6):
+        with pytest.raises(argus.ArgusError):
+            argus.batch_candidate(bad)

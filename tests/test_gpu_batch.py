@@ -6,6 +6,8 @@ max|dK|/max|K| <= 1e-4 and difference RMS <= 1e-4 sigma; with FP32 row
 moments (small systems amplify their rounding) 3e-3 and 1e-3 sigma; both:
 difference max <= 1e-2 sigma, masks bit-exact, chi^2 relative <= 1e-5.  Cutout sides are drawn log-uniform (ragged sizes,
 several tiles each) from three cameras' frames with different seeing."""
+import json
+
 import numpy as np
 import pytest
 
@@ -222,3 +224,35 @@ def test_batch_keeps_its_basis_across_other_fits(ctx, frames):
         ok = o["dm"] == 0
         err = (gD[ok] - o["D"][ok]) / np.sqrt(o["V"][ok])
         assert np.sqrt(np.mean(err ** 2)) <= RMS_TOL[argus.FP64]
+
+
+def test_batch_tuning_cache(frames, tmp_path):
+    """The autotuner's outcome (choice and every candidate's time) is stored
+    under a key naming the device, the HIP runtime, the kernel and the size
+    bucket, in a JSON-lines file; a new context reading that file takes the
+    stored choice without timing and gives bit-identical outputs."""
+    path = tmp_path / "tune.jsonl"
+    path.write_text("not an entry\n")             # lines that do not parse are skipped
+    cut = _cutouts(frames, 6, 400)
+    c1 = argus.Context(0)
+    c1.set_tune_cache(path)
+    b1, (r1,) = _run(c1, frames, cut)
+    ms1, hit1 = b1.tuning()
+    choice, best, ncand = b1.info()
+    assert not hit1 and len(ms1) == ncand and min(ms1) > 0 and best == ms1[choice] == min(ms1)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2
+    entry = json.loads(lines[1])
+    assert entry["choice"] == choice and len(entry["ms"]) == ncand
+    for part in ("device=gfx", ";hip=", ";kernel=batch;h=7;", ";log2n="):
+        assert part in entry["key"], entry["key"]
+    c2 = argus.Context(0)
+    c2.set_tune_cache(path)
+    b2, (r2,) = _run(c2, frames, cut)
+    ms2, hit2 = b2.tuning()
+    assert hit2 and b2.info()[0] == choice and ms2 == pytest.approx(ms1, rel=1e-5)
+    for k in r1:
+        assert np.array_equal(r1[k], r2[k]), k
+    assert len(path.read_text().splitlines()) == 2   # nothing new stored
+    for c in (c1, c2):
+        c.close()
