@@ -81,13 +81,37 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
         B0[ks] = *(const bf16x8 *)&a.w[col * KP + ks * 32 + 8 * g];
         B1[ks] = *(const bf16x8 *)&a.w[(16 + col) * KP + ks * 32 + 8 * g];
     }
-    for (int i = tid; i < CS::ACT; i += NT) act[i] = (bf16)0.f;
+    for (int i = tid; i < CS::ACT / 8; i += NT) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const bf16 *src = a.in + (size_t)s * a.npx * CIN;
-    for (int i = tid; i < a.npx * CIN; i += NT) {
-        int p = i / CIN, c = i % CIN;
-        int y = p / W, x = p % W;
-        act[((y + 1) * PW + (x + 1)) * CIN + c] = src[i];
+    if constexpr (CIN % 8 == 0) {
+        // 16-byte pieces (8 channels of a pixel), eight loads in flight per
+        // thread before their LDS stores
+        constexpr int C8 = CIN / 8, U = 8;
+        const int n8 = a.npx * C8;
+        const uint4 *src4 = (const uint4 *)src;
+        for (int i0 = tid; i0 < n8; i0 += NT * U) {
+            uint4 v[U];
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const int i = i0 + e * NT;
+                v[e] = i < n8 ? src4[i] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const int i = i0 + e * NT;
+                if (i < n8) {
+                    const int p = i / C8, c8 = i % C8, y = p / W, x = p % W;
+                    *(uint4 *)&act[((y + 1) * PW + (x + 1)) * CIN + 8 * c8] = v[e];
+                }
+            }
+        }
+    } else {
+        for (int i = tid; i < a.npx * CIN; i += NT) {
+            int p = i / CIN, c = i % CIN;
+            int y = p / W, x = p % W;
+            act[((y + 1) * PW + (x + 1)) * CIN + c] = src[i];
+        }
     }
     __syncthreads();
     bf16 *dst = a.out + (size_t)s * a.npx * 32;
@@ -201,21 +225,66 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     float db = 0.f;                             // channel tid & 31, pixels tid >> 5 mod 8
-    for (int i = tid; i < 32 * W * DW; i += NT) dzl[i] = (bf16)0.f;
-    for (int i = tid; i < CIN * AH * AW; i += NT) al[i] = (bf16)0.f;
+    for (int i = tid; i < 32 * W * DW / 8; i += NT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < CIN * AH * AW / 8; i += NT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     for (int s = gi; s < a.S; s += a.G) {
         const int n = t * a.S + s;
         if (!a.valid[n]) continue;                       // uniform across the block
         const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
         const bf16 *as = a.ain + (size_t)n * a.npx * CIN;
-        for (int i = tid; i < a.npx * 32; i += NT) {
-            int p = i >> 5, o = i & 31;
-            dzl[(o * W + p / W) * DW + p % W] = dzs[i];
+        // a thread takes whole pixels (every channel: 16-byte loads) and
+        // spreads them into the channel-first tiles; for one channel the
+        // lanes of a wave write consecutive pixels (no bank conflicts)
+        constexpr int PXT = 4;                           // pixels per thread in flight
+        for (int p0 = tid; p0 < a.npx; p0 += NT * PXT) {
+            uint4 dv[PXT][4];
+#pragma unroll
+            for (int e = 0; e < PXT; ++e) {
+                const int p = p0 + e * NT;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    dv[e][q] = p < a.npx ? ((const uint4 *)(dzs + (size_t)p * 32))[q]
+                                         : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int e = 0; e < PXT; ++e) {
+                const int p = p0 + e * NT;
+                if (p < a.npx) {
+                    const int y = p / W, x = p % W;
+                    const bf16 *v = (const bf16 *)dv[e];
+#pragma unroll
+                    for (int o = 0; o < 32; ++o) dzl[(o * W + y) * DW + x] = v[o];
+                }
+            }
         }
-        for (int i = tid; i < a.npx * CIN; i += NT) {
-            int p = i / CIN, c = i % CIN;
-            al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
+        if constexpr (CIN == 32) {
+            for (int p0 = tid; p0 < a.npx; p0 += NT * PXT) {
+                uint4 av[PXT][4];
+#pragma unroll
+                for (int e = 0; e < PXT; ++e) {
+                    const int p = p0 + e * NT;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        av[e][q] = p < a.npx ? ((const uint4 *)(as + (size_t)p * 32))[q]
+                                             : make_uint4(0u, 0u, 0u, 0u);
+                }
+#pragma unroll
+                for (int e = 0; e < PXT; ++e) {
+                    const int p = p0 + e * NT;
+                    if (p < a.npx) {
+                        const int y = p / W, x = p % W;
+                        const bf16 *v = (const bf16 *)av[e];
+#pragma unroll
+                        for (int c = 0; c < 32; ++c) al[(c * AH + y + 1) * AW + x + 1] = v[c];
+                    }
+                }
+            }
+        } else {
+            for (int i = tid; i < a.npx * CIN; i += NT) {
+                int p = i / CIN, c = i % CIN;
+                al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
+            }
         }
         __syncthreads();
         {

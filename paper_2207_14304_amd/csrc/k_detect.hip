@@ -230,84 +230,91 @@ __global__ __launch_bounds__(64) void scan_top_kernel(DetArgs a) {
 template <bool SRC>
 __global__ __launch_bounds__(NTHR) void detect_emit_kernel(DetArgs a) {
     const int lane = threadIdx.x & 63;
-    // a wave walks segments with a stride of all waves (most hold no candidate)
+    // a wave reads the counts of 64 segments at once (one load per lane, most
+    // segments hold no candidate) and visits those with candidates; groups of
+    // 64 segments are strided over all waves
     const int nw = gridDim.x * (NTHR / 64);
-    for (int seg = blockIdx.x * (NTHR / 64) + (threadIdx.x >> 6); seg < a.nseg; seg += nw) {
-        if (a.counts[seg] == 0) continue;
-        int idx = a.tile_off[seg / STILE] + a.local[seg];
-        const int y = seg / a.nsx, x0 = (seg % a.nsx) * SEG;
-        const int64_t orow = (int64_t)y * a.pitch;
-        const int K = 2 * a.r + 1;
-        for (int c0 = 0; c0 < SEG && idx < a.cap; c0 += 64) {
-            const int x = x0 + c0 + lane;
-            const bool isc = x < a.W && (a.det[orow + x] & ARGUS_CAND);
-            uint64_t bal = __ballot(isc);
-            while (bal && idx < a.cap) {
-                const int l = __builtin_ctzll(bal);
-                bal &= bal - 1;
-                const int cx = x0 + c0 + l;
-                // PSF-weighted flux over unmasked in-image pixels of the window
-                double q = 0.0, f = 0.0;
-                for (int t = lane; t < K * K; t += 64) {
-                    int xx = cx + t % K - a.r, yy = y + t / K - a.r;
-                    if (xx < 0 || xx >= a.W || yy < 0 || yy >= a.H) continue;
-                    int64_t o = (int64_t)yy * a.pitch + xx;
-                    float V = a.dvar[o];
-                    if (a.dmask[o] != 0 || !(V > 0.f)) continue;
-                    double p = (double)a.psf[t];
-                    q += p * p / (double)V;
-                    f += p * (double)d_at<SRC>(a, o, xx, yy) / (double)V;
-                }
-                // source centroid: max(D, 0) over the unmasked in-image 3 x 3
-                double cs = 0.0, cxs = 0.0, cys = 0.0;
-                if constexpr (SRC) {
-                    if (lane < 9) {
-                        const int u = lane % 3 - 1, v = lane / 3 - 1, xx = cx + u, yy = y + v;
-                        if (xx >= 0 && xx < a.W && yy >= 0 && yy < a.H) {
-                            const int64_t o = (int64_t)yy * a.pitch + xx;
-                            const float V = a.dvar[o];
-                            if (a.dmask[o] == 0 && V > 0.f) {
-                                const double d = fmax((double)d_at<SRC>(a, o, xx, yy), 0.0);
-                                cs = d;
-                                cxs = u * d;
-                                cys = v * d;
+    for (int s0 = (blockIdx.x * (NTHR / 64) + (threadIdx.x >> 6)) * 64; s0 < a.nseg; s0 += nw * 64) {
+        const bool has = s0 + lane < a.nseg && a.counts[s0 + lane] != 0;
+        uint64_t segs = __ballot(has);
+        while (segs) {
+            const int seg = s0 + __builtin_ctzll(segs);
+            segs &= segs - 1;
+            int idx = a.tile_off[seg / STILE] + a.local[seg];
+            const int y = seg / a.nsx, x0 = (seg % a.nsx) * SEG;
+            const int64_t orow = (int64_t)y * a.pitch;
+            const int K = 2 * a.r + 1;
+            for (int c0 = 0; c0 < SEG && idx < a.cap; c0 += 64) {
+                const int x = x0 + c0 + lane;
+                const bool isc = x < a.W && (a.det[orow + x] & ARGUS_CAND);
+                uint64_t bal = __ballot(isc);
+                while (bal && idx < a.cap) {
+                    const int l = __builtin_ctzll(bal);
+                    bal &= bal - 1;
+                    const int cx = x0 + c0 + l;
+                    // PSF-weighted flux over unmasked in-image pixels of the window
+                    double q = 0.0, f = 0.0;
+                    for (int t = lane; t < K * K; t += 64) {
+                        int xx = cx + t % K - a.r, yy = y + t / K - a.r;
+                        if (xx < 0 || xx >= a.W || yy < 0 || yy >= a.H) continue;
+                        int64_t o = (int64_t)yy * a.pitch + xx;
+                        float V = a.dvar[o];
+                        if (a.dmask[o] != 0 || !(V > 0.f)) continue;
+                        double p = (double)a.psf[t];
+                        q += p * p / (double)V;
+                        f += p * (double)d_at<SRC>(a, o, xx, yy) / (double)V;
+                    }
+                    // source centroid: max(D, 0) over the unmasked in-image 3 x 3
+                    double cs = 0.0, cxs = 0.0, cys = 0.0;
+                    if constexpr (SRC) {
+                        if (lane < 9) {
+                            const int u = lane % 3 - 1, v = lane / 3 - 1, xx = cx + u, yy = y + v;
+                            if (xx >= 0 && xx < a.W && yy >= 0 && yy < a.H) {
+                                const int64_t o = (int64_t)yy * a.pitch + xx;
+                                const float V = a.dvar[o];
+                                if (a.dmask[o] == 0 && V > 0.f) {
+                                    const double d = fmax((double)d_at<SRC>(a, o, xx, yy), 0.0);
+                                    cs = d;
+                                    cxs = u * d;
+                                    cys = v * d;
+                                }
                             }
                         }
                     }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    q += __shfl_xor(q, off);
-                    f += __shfl_xor(f, off);
-                    if constexpr (SRC) {
-                        cs += __shfl_xor(cs, off);
-                        cxs += __shfl_xor(cxs, off);
-                        cys += __shfl_xor(cys, off);
+                    for (int off = 32; off > 0; off >>= 1) {
+                        q += __shfl_xor(q, off);
+                        f += __shfl_xor(f, off);
+                        if constexpr (SRC) {
+                            cs += __shfl_xor(cs, off);
+                            cxs += __shfl_xor(cxs, off);
+                            cys += __shfl_xor(cys, off);
+                        }
                     }
-                }
-                if (lane == 0) {
-                    const float fl = q > 0.0 ? (float)(f / q) : __builtin_nanf("");
-                    const float fe = q > 0.0 ? (float)(1.0 / sqrt(q)) : __builtin_nanf("");
-                    if constexpr (SRC) {
-                        argus_source c;
-                        c.x = cx;
-                        c.y = y;
-                        c.xc = cs > 0.0 ? (float)(cx + cxs / cs) : __builtin_nanf("");
-                        c.yc = cs > 0.0 ? (float)(y + cys / cs) : __builtin_nanf("");
-                        c.snr = snr_at<SRC>(a, cx, y);
-                        c.flux = fl;
-                        c.flux_err = fe;
-                        a.srcs[idx] = c;
-                    } else {
-                        argus_candidate c;
-                        c.x = cx;
-                        c.y = y;
-                        c.snr = snr_at<SRC>(a, cx, y);
-                        c.flux = fl;
-                        c.flux_err = fe;
-                        a.cands[idx] = c;
+                    if (lane == 0) {
+                        const float fl = q > 0.0 ? (float)(f / q) : __builtin_nanf("");
+                        const float fe = q > 0.0 ? (float)(1.0 / sqrt(q)) : __builtin_nanf("");
+                        if constexpr (SRC) {
+                            argus_source c;
+                            c.x = cx;
+                            c.y = y;
+                            c.xc = cs > 0.0 ? (float)(cx + cxs / cs) : __builtin_nanf("");
+                            c.yc = cs > 0.0 ? (float)(y + cys / cs) : __builtin_nanf("");
+                            c.snr = snr_at<SRC>(a, cx, y);
+                            c.flux = fl;
+                            c.flux_err = fe;
+                            a.srcs[idx] = c;
+                        } else {
+                            argus_candidate c;
+                            c.x = cx;
+                            c.y = y;
+                            c.snr = snr_at<SRC>(a, cx, y);
+                            c.flux = fl;
+                            c.flux_err = fe;
+                            a.cands[idx] = c;
+                        }
                     }
+                    ++idx;
                 }
-                ++idx;
             }
         }
     }
@@ -353,8 +360,8 @@ int launch_detect_any(argus_ctx *ctx, argus_dims d, const float *diff, const flo
     argus_time_begin(ctx);
     hipLaunchKernelGGL(scan_tiles_kernel, dim3(a.ntile), dim3(NTHR), 0, ctx->stream, a);
     hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(64), 0, ctx->stream, a);
-    // enough waves to fill the device a few times over; each walks segments
-    const int eblocks = std::max(1, std::min((a.nseg + 3) / 4, 8 * std::max(ctx->n_cu, 1)));
+    // one wave per 64 segments, at most enough to fill the device a few times over
+    const int eblocks = std::max(1, std::min((a.nseg + 255) / 256, 8 * std::max(ctx->n_cu, 1)));
     if (src)
         hipLaunchKernelGGL(detect_emit_kernel<true>, dim3(eblocks), dim3(NTHR), 0, ctx->stream, a);
     else
