@@ -233,52 +233,41 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
         if (!a.valid[n]) continue;                       // uniform across the block
         const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
         const bf16 *as = a.ain + (size_t)n * a.npx * CIN;
-        // a thread takes whole pixels (every channel: 16-byte loads) and
-        // spreads them into the channel-first tiles; for one channel the
-        // lanes of a wave write consecutive pixels (no bank conflicts)
-        constexpr int PXT = 4;                           // pixels per thread in flight
-        for (int p0 = tid; p0 < a.npx; p0 += NT * PXT) {
-            uint4 dv[PXT][4];
+        // a thread takes a pair of horizontally adjacent pixels (every
+        // channel: 16-byte loads) and writes each channel's pair as one
+        // 4-byte word of the channel-first tiles; for one channel the lanes of
+        // a wave write consecutive words (no bank conflicts).  dZ pairs are
+        // x = (2m, 2m+1), the input's x = (2m-1, 2m) (its tile is shifted by
+        // the zero border); pixels outside the stamp read as zero.
+        auto load32 = [&](const bf16 *base, int y, int x, uint4 (&v)[4]) {
+            const bool in = x >= 0 && x < W;
 #pragma unroll
-            for (int e = 0; e < PXT; ++e) {
-                const int p = p0 + e * NT;
+            for (int q = 0; q < 4; ++q)
+                v[q] = in ? ((const uint4 *)(base + (size_t)(y * W + x) * 32))[q] : make_uint4(0u, 0u, 0u, 0u);
+        };
+        auto pack = [](const uint4 (&a)[4], const uint4 (&b)[4], int o) -> uint32_t {
+            const uint32_t wa = (&a[o >> 3].x)[(o >> 1) & 3], wb = (&b[o >> 3].x)[(o >> 1) & 3];
+            return (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
+        };
+        constexpr int NPAIR = W * 16;                    // 31 rows x 16 pairs
+        for (int q0 = tid; q0 < NPAIR; q0 += NT) {
+            const int y = q0 / 16, m = q0 % 16;
+            uint4 v0[4], v1[4];
+            load32(dzs, y, 2 * m, v0);
+            load32(dzs, y, 2 * m + 1, v1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    dv[e][q] = p < a.npx ? ((const uint4 *)(dzs + (size_t)p * 32))[q]
-                                         : make_uint4(0u, 0u, 0u, 0u);
-            }
-#pragma unroll
-            for (int e = 0; e < PXT; ++e) {
-                const int p = p0 + e * NT;
-                if (p < a.npx) {
-                    const int y = p / W, x = p % W;
-                    const bf16 *v = (const bf16 *)dv[e];
-#pragma unroll
-                    for (int o = 0; o < 32; ++o) dzl[(o * W + y) * DW + x] = v[o];
-                }
-            }
+            for (int o = 0; o < 32; ++o)
+                *(uint32_t *)&dzl[(o * W + y) * DW + 2 * m] = pack(v0, v1, o);
         }
         if constexpr (CIN == 32) {
-            for (int p0 = tid; p0 < a.npx; p0 += NT * PXT) {
-                uint4 av[PXT][4];
+            for (int q0 = tid; q0 < NPAIR; q0 += NT) {
+                const int y = q0 / 16, m = q0 % 16;
+                uint4 v0[4], v1[4];
+                load32(as, y, 2 * m - 1, v0);
+                load32(as, y, 2 * m, v1);
 #pragma unroll
-                for (int e = 0; e < PXT; ++e) {
-                    const int p = p0 + e * NT;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        av[e][q] = p < a.npx ? ((const uint4 *)(as + (size_t)p * 32))[q]
-                                             : make_uint4(0u, 0u, 0u, 0u);
-                }
-#pragma unroll
-                for (int e = 0; e < PXT; ++e) {
-                    const int p = p0 + e * NT;
-                    if (p < a.npx) {
-                        const int y = p / W, x = p % W;
-                        const bf16 *v = (const bf16 *)av[e];
-#pragma unroll
-                        for (int c = 0; c < 32; ++c) al[(c * AH + y + 1) * AW + x + 1] = v[c];
-                    }
-                }
+                for (int c = 0; c < 32; ++c)
+                    *(uint32_t *)&al[(c * AH + y + 1) * AW + 2 * m] = pack(v0, v1, c);
             }
         } else {
             for (int i = tid; i < a.npx * CIN; i += NT) {
@@ -479,13 +468,37 @@ __global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a) {
     }
 }
 
-// fixed-order sum of per-tile partials into one gradient segment
-__global__ void cnn_reduce_kernel(const float *part, int stride, int len, int T, float *dst) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
+// Fixed-order sum of T per-tile partials into one gradient segment: a
+// workgroup takes 32 consecutive entries; its 8 thread groups sum 8
+// consecutive ranges of the partials (each in order, several loads in
+// flight), then the 8 range sums are added in order.
+constexpr int RED_W = 32, RED_G = 8;
+__global__ __launch_bounds__(RED_W * RED_G) void cnn_reduce_kernel(const float *part, int stride,
+                                                                   int len, int T, float *dst) {
+    __shared__ float rs[RED_G][RED_W];
+    const int j = threadIdx.x % RED_W, g = threadIdx.x / RED_W;
+    const int i = blockIdx.x * RED_W + j;
+    const int t0 = (int)((int64_t)g * T / RED_G), t1 = (int)((int64_t)(g + 1) * T / RED_G);
     float s = 0.f;
-    for (int t = 0; t < T; ++t) s += part[(size_t)t * stride + i];
-    dst[i] = s;
+    if (i < len) {
+        int t = t0;
+        for (; t + 8 <= t1; t += 8) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = part[(size_t)(t + q) * stride + i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += v[q];
+        }
+        for (; t < t1; ++t) s += part[(size_t)t * stride + i];
+    }
+    rs[g][j] = s;
+    __syncthreads();
+    if (g == 0 && i < len) {
+        float tot = 0.f;
+#pragma unroll
+        for (int q = 0; q < RED_G; ++q) tot += rs[q][j];
+        dst[i] = tot;
+    }
 }
 
 __global__ void cnn_loss_kernel(const double *part, int T, double *loss) {
@@ -1097,8 +1110,8 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
     hipLaunchKernelGGL(cnn_dz4_kernel, dim3(T * c->S), dim3(NT), 0, ctx->stream, ha);
     const int hlen = c->nout * 32 + c->nout;
-    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((hlen + 255) / 256), dim3(256), 0, ctx->stream,
-                       (const float *)c->part, hlen, hlen, T, c->grad + c->hw_off);
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((hlen + RED_W - 1) / RED_W), dim3(RED_W * RED_G), 0,
+                       ctx->stream, (const float *)c->part, hlen, hlen, T, c->grad + c->hw_off);
     hipLaunchKernelGGL(cnn_loss_kernel, dim3(1), dim3(64), 0, ctx->stream,
                        (const double *)c->loss_part, T, loss);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
@@ -1116,8 +1129,9 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
         rc = l == 0 ? wgrad_launch<2>(ctx, wa, T) : wgrad_launch<32>(ctx, wa, T);
         if (rc) return rc;
         const int len = 32 * 9 * c->cin[l] + 32;
-        hipLaunchKernelGGL(cnn_reduce_kernel, dim3((len + 255) / 256), dim3(256), 0, ctx->stream,
-                           (const float *)c->part, len, len, T * WG_GROUPS, c->grad + c->w_off[l]);
+        hipLaunchKernelGGL(cnn_reduce_kernel, dim3((len + RED_W - 1) / RED_W), dim3(RED_W * RED_G), 0,
+                           ctx->stream, (const float *)c->part, len, len, T * WG_GROUPS,
+                           c->grad + c->w_off[l]);
         ARGUS_HIP_CHECK(ctx, hipGetLastError());
         if (l > 0) {
             ConvArgs ca;
