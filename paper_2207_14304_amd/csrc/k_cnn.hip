@@ -74,12 +74,13 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
     const int s = blockIdx.x, tid = threadIdx.x;
     if (!a.valid[s]) return;
     const int lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
-    // B fragments: output channels col and 16+col, k = ks*32 + 8g .. +7
+    // B fragments: output channels 2 col (B0) and 2 col + 1 (B1), k = ks*32 +
+    // 8g .. +7, so a lane's two results of a pixel are adjacent channels
     bf16x8 B0[KS], B1[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        B0[ks] = *(const bf16x8 *)&a.w[col * KP + ks * 32 + 8 * g];
-        B1[ks] = *(const bf16x8 *)&a.w[(16 + col) * KP + ks * 32 + 8 * g];
+        B0[ks] = *(const bf16x8 *)&a.w[(2 * col) * KP + ks * 32 + 8 * g];
+        B1[ks] = *(const bf16x8 *)&a.w[(2 * col + 1) * KP + ks * 32 + 8 * g];
     }
     for (int i = tid; i < CS::ACT / 8; i += NT) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
@@ -115,63 +116,86 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
     }
     __syncthreads();
     bf16 *dst = a.out + (size_t)s * a.npx * 32;
-    for (int t = wave; t * 16 < a.npx; t += 4) {
-        floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        const int p = t * 16 + col;
-        const int y = p / W, x = p % W;
+    // A operand of tile t, step ks: pixel t*16 + col, inputs k = ks*32 + 8g .. +7
+    auto load_a = [&](int t, int ks) -> bf16x8 {
+        bf16x8 A;
+        const int p = t * 16 + col, y = p / W, x = p % W;
         const bool pin = p < a.npx;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            bf16x8 A;
-            if constexpr (CIN == 32) {
-                const int dy = ks / 3 - 1, dx = ks % 3 - 1;
-                if (pin) {
-                    A = *(const bf16x8 *)&act[((y + 1 + dy) * PW + (x + 1 + dx)) * 32 + 8 * g];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) A[e] = (bf16)0.f;
-                }
+        if constexpr (CIN == 32) {
+            const int dy = ks / 3 - 1, dx = ks % 3 - 1;
+            if (pin) {
+                A = *(const bf16x8 *)&act[((y + 1 + dy) * PW + (x + 1 + dx)) * 32 + 8 * g];
             } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = ks * 32 + 8 * g + e, tap = k / CIN, c = k % CIN;
-                    bf16 v = (bf16)0.f;
-                    if (pin && tap < 9) {
-                        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                        v = act[((y + 1 + dy) * PW + (x + 1 + dx)) * CIN + c];
-                    }
-                    A[e] = v;
-                }
+                for (int e = 0; e < 8; ++e) A[e] = (bf16)0.f;
             }
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0[ks], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[ks], acc1, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = ks * 32 + 8 * g + e, tap = k / CIN, c = k % CIN;
+                bf16 v = (bf16)0.f;
+                if (pin && tap < 9) {
+                    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                    v = act[((y + 1 + dy) * PW + (x + 1 + dx)) * CIN + c];
+                }
+                A[e] = v;
+            }
+        }
+        return A;
+    };
+    // pixels 4g .. 4g+3 of tile t, channels 2 col and 2 col + 1: one 4-byte
+    // store per pixel
+    auto store = [&](int t, const floatx4 &r0, const floatx4 &r1) {
+        float b0 = 0.f, b1 = 0.f;
+        if (MODE == 0) {
+            b0 = a.bias[2 * col];
+            b1 = a.bias[2 * col + 1];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pp = t * 16 + 4 * g + r;
             if (pp >= a.npx) continue;
+            float v0 = r0[r], v1 = r1[r];
+            if (MODE == 0) {
+                v0 = fmaxf(v0 + b0, 0.f);
+                v1 = fmaxf(v1 + b1, 0.f);
+            } else {
+                const uint32_t gw = *(const uint32_t *)&a.gate[((size_t)s * a.npx + pp) * 32 + 2 * col];
+                const bf16 *gv = (const bf16 *)&gw;
+                v0 = bf2f(gv[0]) > 0.f ? v0 : 0.f;
+                v1 = bf2f(gv[1]) > 0.f ? v1 : 0.f;
+            }
+            const bf16 o2[2] = {(bf16)v0, (bf16)v1};
+            *(uint32_t *)&dst[(size_t)pp * 32 + 2 * col] = *(const uint32_t *)o2;
+        }
+    };
+    // two tiles per pass (t and t + 4): four independent accumulator chains
+    const int ntile = (a.npx + 15) / 16;
+    for (int t = wave; t < ntile; t += 8) {
+        const bool two = t + 4 < ntile;                 // uniform across the wave
+        floatx4 p0 = {0.f, 0.f, 0.f, 0.f}, p1 = p0, q0 = p0, q1 = p0;
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int o = nt * 16 + col;
-                float val = nt ? acc1[r] : acc0[r];
-                if (MODE == 0) {
-                    val = fmaxf(val + a.bias[o], 0.f);
-                } else {
-                    const float gv = bf2f(a.gate[((size_t)s * a.npx + pp) * 32 + o]);
-                    val = gv > 0.f ? val : 0.f;
-                }
-                dst[(size_t)pp * 32 + o] = (bf16)val;
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 A = load_a(t, ks);
+            p0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0[ks], p0, 0, 0, 0);
+            p1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[ks], p1, 0, 0, 0);
+            if (two) {
+                const bf16x8 A2 = load_a(t + 4, ks);
+                q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, B0[ks], q0, 0, 0, 0);
+                q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, B1[ks], q1, 0, 0, 0);
             }
         }
+        store(t, p0, p1);
+        if (two) store(t + 4, q0, q1);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Weight gradients: G workgroups per tile, workgroup g taking stamps g,
 // g + G, ... of its tile (the k range).  dW[o][tap][c] = sum_p dZ[p][o]
-// A_in[p + off(tap)][c]; db[o] = sum_p dZ[p][o].  K steps are image rows
-// (32 columns, the last one zero).  The T G partials are summed afterwards in
-// a fixed order.
+// A_in[p + off(tap)][c]; db[o] = sum_p dZ[p][o], as one more MFMA tile whose
+// B operand is all ones.  K steps are image rows (32 columns, the last one
+// zero).  The T G partials are summed afterwards in a fixed order.
 constexpr int WG_GROUPS = 8;
 
 struct WgradArgs {
@@ -214,17 +238,15 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
     extern __shared__ __align__(16) bf16 sm[];
     bf16 *dzl = sm;                             // [32][31][32]   channel-first dZ
     bf16 *al = sm + 32 * W * DW;                // [CIN][33][40]  channel-first input
-    __shared__ float dbp[NT];
     const int b = blockIdx.x, t = b / a.G, gi = b % a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, g = lane >> 4;
-    constexpr int NMAX = (NTL + 3) / 4;
+    constexpr int NMAX = (NTL + 1 + 3) / 4;             // the NTL weight tiles and the bias tile
     floatx4 acc[2][NMAX];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float db = 0.f;                             // channel tid & 31, pixels tid >> 5 mod 8
     for (int i = tid; i < 32 * W * DW / 8; i += NT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = tid; i < CIN * AH * AW / 8; i += NT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
@@ -276,21 +298,21 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
             }
         }
         __syncthreads();
-        {
-            const int o = tid & 31;
-            for (int p = tid >> 5; p < a.npx; p += NT / 32)
-                db += bf2f(dzl[(o * W + p / W) * DW + p % W]);
-        }
         for (int y = 0; y < W; ++y) {
             bf16x8 A0 = *(const bf16x8 *)&dzl[(col * W + y) * DW + 8 * g];
             bf16x8 A1 = *(const bf16x8 *)&dzl[((16 + col) * W + y) * DW + 8 * g];
 #pragma unroll
             for (int jj = 0; jj < NMAX; ++jj) {
                 const int nt = wave + 4 * jj;
-                if (nt >= NTL) break;
+                if (nt > NTL) break;
                 const int j = nt * 16 + col;
                 bf16x8 B;
-                if constexpr (CIN == 32) {
+                if (nt == NTL) {
+                    // the bias tile: every column of B is one, so each column
+                    // of the product is db[o] = sum_p dZ[p][o]
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) B[e] = (bf16)1.f;
+                } else if constexpr (CIN == 32) {
                     // one tap per 16-column tile: dy, dx uniform across the wave
                     const int tap = (nt * 16) / 32, c = j % 32, dy = tap / 3 - 1, dx = tap % 3 - 1;
                     B = shifted8(&al[(c * AH + y + 1 + dy) * AW + 8 * g], dx + 1);
@@ -315,20 +337,22 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
 #pragma unroll
     for (int jj = 0; jj < NMAX; ++jj) {
         const int nt = wave + 4 * jj;
-        if (nt >= NTL) break;
+        if (nt > NTL) break;
+        if (nt == NTL) {
+            if (col == 0) {
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) part[32 * NJ + mt * 16 + 4 * g + r] = acc[mt][jj][r];
+            }
+            continue;
+        }
         const int j = nt * 16 + col;
         if (j >= NJ) continue;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[(mt * 16 + 4 * g + r) * NJ + j] = acc[mt][jj][r];
-    }
-    dbp[tid] = db;
-    __syncthreads();
-    if (tid < 32) {
-        float sdb = 0.f;
-        for (int q = 0; q < NT / 32; ++q) sdb += dbp[q * 32 + tid];
-        part[32 * NJ + tid] = sdb;
     }
 }
 
