@@ -41,12 +41,13 @@ struct argus_cnn {
 namespace {
 
 constexpr int NT = 256;
+constexpr int CT = 512;        // convolution and weight-gradient workgroups: 8 waves
 
 __device__ __forceinline__ float bf2f(bf16 x) { return (float)x; }
 
 // ---------------------------------------------------------------------------
 // Convolution: one workgroup per stamp; 61 output tiles of 16 pixels x 32
-// channels spread over the 4 waves; K = 9 * CIN (padded to 32) per tile.
+// channels spread over the 8 waves; K = 9 * CIN (padded to 32) per tile.
 // The weight fragments of every K step stay in registers for the whole
 // stamp (loaded once from global memory), so the tile loop reads only the
 // activations from LDS, and two workgroups fit a CU.
@@ -66,7 +67,7 @@ struct ConvShape {
 };
 
 template <int CIN, int MODE>
-__global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
     using CS = ConvShape<CIN>;
     constexpr int KP = CS::KP, KS = CS::KS, W = 31, PW = CS::PW;
     extern __shared__ __align__(16) bf16 sm[];
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
         B0[ks] = *(const bf16x8 *)&a.w[(2 * col) * KP + ks * 32 + 8 * g];
         B1[ks] = *(const bf16x8 *)&a.w[(2 * col + 1) * KP + ks * 32 + 8 * g];
     }
-    for (int i = tid; i < CS::ACT / 8; i += NT) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < CS::ACT / 8; i += CT) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const bf16 *src = a.in + (size_t)s * a.npx * CIN;
     if constexpr (CIN % 8 == 0) {
@@ -91,16 +92,16 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
         constexpr int C8 = CIN / 8, U = 8;
         const int n8 = a.npx * C8;
         const uint4 *src4 = (const uint4 *)src;
-        for (int i0 = tid; i0 < n8; i0 += NT * U) {
+        for (int i0 = tid; i0 < n8; i0 += CT * U) {
             uint4 v[U];
 #pragma unroll
             for (int e = 0; e < U; ++e) {
-                const int i = i0 + e * NT;
+                const int i = i0 + e * CT;
                 v[e] = i < n8 ? src4[i] : make_uint4(0u, 0u, 0u, 0u);
             }
 #pragma unroll
             for (int e = 0; e < U; ++e) {
-                const int i = i0 + e * NT;
+                const int i = i0 + e * CT;
                 if (i < n8) {
                     const int p = i / C8, c8 = i % C8, y = p / W, x = p % W;
                     *(uint4 *)&act[((y + 1) * PW + (x + 1)) * CIN + 8 * c8] = v[e];
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
             }
         }
     } else {
-        for (int i = tid; i < a.npx * CIN; i += NT) {
+        for (int i = tid; i < a.npx * CIN; i += CT) {
             int p = i / CIN, c = i % CIN;
             int y = p / W, x = p % W;
             act[((y + 1) * PW + (x + 1)) * CIN + c] = src[i];
@@ -143,9 +144,20 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
         }
         return A;
     };
+    // the backward pass's gates (channels 2 col, 2 col + 1 of pixels 4g ..
+    // 4g+3 of tile t), loaded before the tile's products so they are in flight
+    auto load_gate = [&](int t, uint32_t (&gw)[4]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = t * 16 + 4 * g + r;
+            gw[r] = (MODE == 1 && pp < a.npx)
+                        ? *(const uint32_t *)&a.gate[((size_t)s * a.npx + pp) * 32 + 2 * col]
+                        : 0u;
+        }
+    };
     // pixels 4g .. 4g+3 of tile t, channels 2 col and 2 col + 1: one 4-byte
     // store per pixel
-    auto store = [&](int t, const floatx4 &r0, const floatx4 &r1) {
+    auto store = [&](int t, const floatx4 &r0, const floatx4 &r1, const uint32_t (&gw)[4]) {
         float b0 = 0.f, b1 = 0.f;
         if (MODE == 0) {
             b0 = a.bias[2 * col];
@@ -160,8 +172,7 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
                 v0 = fmaxf(v0 + b0, 0.f);
                 v1 = fmaxf(v1 + b1, 0.f);
             } else {
-                const uint32_t gw = *(const uint32_t *)&a.gate[((size_t)s * a.npx + pp) * 32 + 2 * col];
-                const bf16 *gv = (const bf16 *)&gw;
+                const bf16 *gv = (const bf16 *)&gw[r];
                 v0 = bf2f(gv[0]) > 0.f ? v0 : 0.f;
                 v1 = bf2f(gv[1]) > 0.f ? v1 : 0.f;
             }
@@ -169,10 +180,14 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
             *(uint32_t *)&dst[(size_t)pp * 32 + 2 * col] = *(const uint32_t *)o2;
         }
     };
-    // two tiles per pass (t and t + 4): four independent accumulator chains
+    // two tiles per pass (t and t + NW): four independent accumulator chains
+    constexpr int NW = CT / 64;
     const int ntile = (a.npx + 15) / 16;
-    for (int t = wave; t < ntile; t += 8) {
-        const bool two = t + 4 < ntile;                 // uniform across the wave
+    for (int t = wave; t < ntile; t += 2 * NW) {
+        const bool two = t + NW < ntile;                // uniform across the wave
+        uint32_t g0[4], g1[4];
+        load_gate(t, g0);
+        if (two) load_gate(t + NW, g1);
         floatx4 p0 = {0.f, 0.f, 0.f, 0.f}, p1 = p0, q0 = p0, q1 = p0;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -180,13 +195,13 @@ __global__ __launch_bounds__(NT) void cnn_conv_kernel(ConvArgs a) {
             p0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0[ks], p0, 0, 0, 0);
             p1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[ks], p1, 0, 0, 0);
             if (two) {
-                const bf16x8 A2 = load_a(t + 4, ks);
+                const bf16x8 A2 = load_a(t + NW, ks);
                 q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, B0[ks], q0, 0, 0, 0);
                 q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, B1[ks], q1, 0, 0, 0);
             }
         }
-        store(t, p0, p1);
-        if (two) store(t + 4, q0, q1);
+        store(t, p0, p1, g0);
+        if (two) store(t + NW, q0, q1, g1);
     }
 }
 
@@ -232,7 +247,7 @@ __device__ __forceinline__ bf16x8 shifted8(const bf16 *p, int e) {
 }
 
 template <int CIN>
-__global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
+__global__ __launch_bounds__(CT) void cnn_wgrad_kernel(WgradArgs a) {
     using WS = WgradShape<CIN>;
     constexpr int NJ = WS::NJ, NTL = WS::NTL, W = WS::W, DW = WS::DW, AW = WS::AW, AH = WS::AH;
     extern __shared__ __align__(16) bf16 sm[];
@@ -241,14 +256,14 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
     const int b = blockIdx.x, t = b / a.G, gi = b % a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, g = lane >> 4;
-    constexpr int NMAX = (NTL + 1 + 3) / 4;             // the NTL weight tiles and the bias tile
+    constexpr int NWV = CT / 64, NMAX = (NTL + 1 + NWV - 1) / NWV;   // weight tiles and the bias tile
     floatx4 acc[2][NMAX];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int i = tid; i < 32 * W * DW / 8; i += NT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (int i = tid; i < CIN * AH * AW / 8; i += NT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < 32 * W * DW / 8; i += CT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < CIN * AH * AW / 8; i += CT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     for (int s = gi; s < a.S; s += a.G) {
         const int n = t * a.S + s;
@@ -272,7 +287,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
             return (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
         };
         constexpr int NPAIR = W * 16;                    // 31 rows x 16 pairs
-        for (int q0 = tid; q0 < NPAIR; q0 += NT) {
+        for (int q0 = tid; q0 < NPAIR; q0 += CT) {
             const int y = q0 / 16, m = q0 % 16;
             uint4 v0[4], v1[4];
             load32(dzs, y, 2 * m, v0);
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
                 *(uint32_t *)&dzl[(o * W + y) * DW + 2 * m] = pack(v0, v1, o);
         }
         if constexpr (CIN == 32) {
-            for (int q0 = tid; q0 < NPAIR; q0 += NT) {
+            for (int q0 = tid; q0 < NPAIR; q0 += CT) {
                 const int y = q0 / 16, m = q0 % 16;
                 uint4 v0[4], v1[4];
                 load32(as, y, 2 * m - 1, v0);
@@ -292,7 +307,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
                     *(uint32_t *)&al[(c * AH + y + 1) * AW + 2 * m] = pack(v0, v1, c);
             }
         } else {
-            for (int i = tid; i < a.npx * CIN; i += NT) {
+            for (int i = tid; i < a.npx * CIN; i += CT) {
                 int p = i / CIN, c = i % CIN;
                 al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
             }
@@ -303,7 +318,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
             bf16x8 A1 = *(const bf16x8 *)&dzl[((16 + col) * W + y) * DW + 8 * g];
 #pragma unroll
             for (int jj = 0; jj < NMAX; ++jj) {
-                const int nt = wave + 4 * jj;
+                const int nt = wave + NWV * jj;
                 if (nt > NTL) break;
                 const int j = nt * 16 + col;
                 bf16x8 B;
@@ -336,7 +351,7 @@ __global__ __launch_bounds__(NT) void cnn_wgrad_kernel(WgradArgs a) {
     float *part = a.part + (size_t)b * (32 * NJ + 32);
 #pragma unroll
     for (int jj = 0; jj < NMAX; ++jj) {
-        const int nt = wave + 4 * jj;
+        const int nt = wave + NWV * jj;
         if (nt > NTL) break;
         if (nt == NTL) {
             if (col == 0) {
@@ -871,7 +886,7 @@ int conv_launch(argus_ctx *ctx, const ConvArgs &ca) {
     size_t lds = (size_t)ConvShape<CIN>::ACT * sizeof(bf16);
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_conv_kernel<CIN, MODE>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n), dim3(NT), lds, ctx->stream, ca);
+    hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n), dim3(CT), lds, ctx->stream, ca);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
@@ -881,7 +896,7 @@ int wgrad_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
     size_t lds = WgradShape<CIN>::bytes();
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad_kernel<CIN>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T * wa.G), dim3(NT), lds, ctx->stream, wa);
+    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T * wa.G), dim3(CT), lds, ctx->stream, wa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
