@@ -34,6 +34,7 @@ struct argus_cnn {
     float *pool = nullptr, *dq = nullptr;       // per stamp pooled features, per tile dq
     float *part = nullptr;                      // per tile gradient partials
     double *loss_part = nullptr;
+    int32_t *order = nullptr, *nvalid = nullptr;   // the valid stamps' indices, their count
     int step = 0;
     void *mem = nullptr;
 };
@@ -55,7 +56,7 @@ __device__ __forceinline__ float bf2f(bf16 x) { return (float)x; }
 struct ConvArgs {
     const bf16 *in, *w, *gate;
     const float *bias;
-    const uint8_t *valid;
+    const int32_t *order, *nvalid;              // workgroup b < *nvalid takes stamp order[b]
     bf16 *out;
     int npx, n;                                 // pixels per stamp (961), stamps
 };
@@ -72,8 +73,10 @@ __global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
     constexpr int KP = CS::KP, KS = CS::KS, W = 31, PW = CS::PW;
     extern __shared__ __align__(16) bf16 sm[];
     bf16 *act = sm;                             // [33][33][CIN], zero border
-    const int s = blockIdx.x, tid = threadIdx.x;
-    if (!a.valid[s]) return;
+    // the valid stamps come first in the grid (compacted order); the rest of
+    // the workgroups leave at once
+    if ((int)blockIdx.x >= *a.nvalid) return;
+    const int s = a.order[blockIdx.x], tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
     // B fragments: output channels 2 col (B0) and 2 col + 1 (B1), k = ks*32 +
     // 8g .. +7, so a lane's two results of a pixel are adjacent channels
@@ -507,6 +510,32 @@ __global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a) {
     }
 }
 
+// Indices of the valid stamps in increasing order and their count (one
+// workgroup; a wave-level ballot scan per 1024-flag chunk).
+constexpr int CMP_T = 1024;
+__global__ __launch_bounds__(CMP_T) void cnn_compact_kernel(const uint8_t *valid, int n, int32_t *order,
+                                                            int32_t *nvalid) {
+    __shared__ int wsum[CMP_T / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int carry = 0;
+    for (int base = 0; base < n; base += CMP_T) {
+        const int i = base + tid;
+        const bool v = i < n && valid[i] != 0;
+        const uint64_t bal = __ballot(v);
+        const int below = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[w] = __builtin_popcountll(bal);
+        __syncthreads();
+        int off = carry;
+        for (int q = 0; q < w; ++q) off += wsum[q];
+        if (v) order[off + below] = i;
+        int tot = 0;
+        for (int q = 0; q < CMP_T / 64; ++q) tot += wsum[q];
+        carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0) *nvalid = carry;
+}
+
 // Fixed-order sum of T per-tile partials into one gradient segment: a
 // workgroup takes 32 consecutive entries; its 8 thread groups sum 8
 // consecutive ranges of the partials (each in order, several loads in
@@ -913,10 +942,13 @@ int cnn_pack(argus_ctx *ctx, argus_cnn *c) {
 
 // forward over T tiles of S stamps; activations stay for the backward pass
 int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t *valid, int T) {
+    hipLaunchKernelGGL(cnn_compact_kernel, dim3(1), dim3(CMP_T), 0, ctx->stream, valid, T * c->S,
+                       c->order, c->nvalid);
     ConvArgs ca;
     ca.npx = c->npx;
     ca.n = T * c->S;
-    ca.valid = valid;
+    ca.order = c->order;
+    ca.nvalid = c->nvalid;
     ca.gate = nullptr;
     for (int l = 0; l < 4; ++l) {
         ca.in = l == 0 ? X : c->act[l - 1];
@@ -1056,6 +1088,7 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     bytes += (size_t)max_tiles * WG_GROUPS * part_stride * sizeof(float);
     bytes += (size_t)max_tiles * sizeof(double) + 4096;
     bytes += (N + max_tiles) * 32 * sizeof(float) + 512;            // pool, dq
+    bytes += N * sizeof(int32_t) + 512;                              // order, nvalid
     if (hipMalloc(&c->mem, bytes) != hipSuccess) {
         delete c;
         return argus_fail(ctx, ARGUS_ENOMEM, "cnn buffers (%zu bytes)", bytes);
@@ -1078,6 +1111,8 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     c->loss_part = (double *)take((size_t)max_tiles * 8);
     c->pool = (float *)take(N * 32 * 4);
     c->dq = (float *)take((size_t)max_tiles * 32 * 4);
+    c->order = (int32_t *)take(N * 4);
+    c->nvalid = (int32_t *)take(64);
     if (hipMemsetAsync(c->mem, 0, 4 * c->P * sizeof(float) + 1024, ctx->stream) != hipSuccess) {
         (void)hipFree(c->mem);
         delete c;
@@ -1178,7 +1213,8 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
             ca.w = c->wt[l];
             ca.gate = c->act[l - 1];
             ca.bias = nullptr;
-            ca.valid = valid;
+            ca.order = c->order;                     // compacted by this step's forward pass
+            ca.nvalid = c->nvalid;
             ca.out = c->dz[cur ^ 1];
             ca.npx = c->npx;
             ca.n = T * c->S;
