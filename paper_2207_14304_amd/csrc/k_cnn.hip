@@ -42,7 +42,8 @@ struct argus_cnn {
 namespace {
 
 constexpr int NT = 256;
-constexpr int CT = 512;        // convolution and weight-gradient workgroups: 8 waves
+constexpr int CT = 512;        // convolution workgroups: 8 waves
+constexpr int WT = 1024;       // weight-gradient workgroups (one per CU by LDS): 16 waves
 
 __device__ __forceinline__ float bf2f(bf16 x) { return (float)x; }
 
@@ -250,7 +251,7 @@ __device__ __forceinline__ bf16x8 shifted8(const bf16 *p, int e) {
 }
 
 template <int CIN>
-__global__ __launch_bounds__(CT) void cnn_wgrad_kernel(WgradArgs a) {
+__global__ __launch_bounds__(WT) void cnn_wgrad_kernel(WgradArgs a) {
     using WS = WgradShape<CIN>;
     constexpr int NJ = WS::NJ, NTL = WS::NTL, W = WS::W, DW = WS::DW, AW = WS::AW, AH = WS::AH;
     extern __shared__ __align__(16) bf16 sm[];
@@ -259,14 +260,14 @@ __global__ __launch_bounds__(CT) void cnn_wgrad_kernel(WgradArgs a) {
     const int b = blockIdx.x, t = b / a.G, gi = b % a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, g = lane >> 4;
-    constexpr int NWV = CT / 64, NMAX = (NTL + 1 + NWV - 1) / NWV;   // weight tiles and the bias tile
+    constexpr int NWV = WT / 64, NMAX = (NTL + 1 + NWV - 1) / NWV;   // weight tiles and the bias tile
     floatx4 acc[2][NMAX];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int i = tid; i < 32 * W * DW / 8; i += CT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (int i = tid; i < CIN * AH * AW / 8; i += CT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < 32 * W * DW / 8; i += WT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < CIN * AH * AW / 8; i += WT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     for (int s = gi; s < a.S; s += a.G) {
         const int n = t * a.S + s;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(CT) void cnn_wgrad_kernel(WgradArgs a) {
             return (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
         };
         constexpr int NPAIR = W * 16;                    // 31 rows x 16 pairs
-        for (int q0 = tid; q0 < NPAIR; q0 += CT) {
+        for (int q0 = tid; q0 < NPAIR; q0 += WT) {
             const int y = q0 / 16, m = q0 % 16;
             uint4 v0[4], v1[4];
             load32(dzs, y, 2 * m, v0);
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(CT) void cnn_wgrad_kernel(WgradArgs a) {
                 *(uint32_t *)&dzl[(o * W + y) * DW + 2 * m] = pack(v0, v1, o);
         }
         if constexpr (CIN == 32) {
-            for (int q0 = tid; q0 < NPAIR; q0 += CT) {
+            for (int q0 = tid; q0 < NPAIR; q0 += WT) {
                 const int y = q0 / 16, m = q0 % 16;
                 uint4 v0[4], v1[4];
                 load32(as, y, 2 * m - 1, v0);
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(CT) void cnn_wgrad_kernel(WgradArgs a) {
                     *(uint32_t *)&al[(c * AH + y + 1) * AW + 2 * m] = pack(v0, v1, c);
             }
         } else {
-            for (int i = tid; i < a.npx * CIN; i += CT) {
+            for (int i = tid; i < a.npx * CIN; i += WT) {
                 int p = i / CIN, c = i % CIN;
                 al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
             }
@@ -925,7 +926,7 @@ int wgrad_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
     size_t lds = WgradShape<CIN>::bytes();
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad_kernel<CIN>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T * wa.G), dim3(CT), lds, ctx->stream, wa);
+    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T * wa.G), dim3(WT), lds, ctx->stream, wa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
