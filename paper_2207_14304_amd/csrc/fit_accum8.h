@@ -28,15 +28,30 @@ constexpr int U8 = 4;       // steps between re-basings of the column windows
 // Steps (and barriers) of a strip: n row steps padded to whole blocks of U8.
 __device__ __forceinline__ int fit8_steps(int n) { return (n + U8 - 1) / U8 * U8; }
 
-template <int D, int HH>
+// TS (the BF16x3 form): the fixed-up basis rows c' and their bf16 hi/lo
+// split are built once per row by the convolution waves, one step after the
+// row's convolution (every MFMA wave used to form and split all 2048 of them
+// itself); with copies of the row's weights they feed the MFMA waves one step
+// later.  The values and their split are those the MFMA waves computed.
+template <int D, int HH, bool TS = false>
 struct FitLds8 {
     static constexpr int K = 2 * HH + 1;
     static constexpr int IN = SW + 2 * HH;               // input row length
     static constexpr int INP = (IN + 3) & ~3;
     static constexpr int CKM = SW + 4;                   // k-major row stride of c
+    static constexpr int CKB = SW + 8;                   // row stride of the bf16 tables (16-byte rows)
+    // TS block per buffer: c' [32][CKM] f32, hi and lo [32][CKB] bf16, copies
+    // of w xt^a [NA][SW] and w s xt^e [NRA][SW]
+    static constexpr int TSB = 32 * CKM + 32 * CKB + (FitShape<D>::NA + FitShape<D>::NRA) * SW;
     float *inrow, *cvec0, *wx0, *wsx0;
     double *wxd0, *wsxd0;
+    float *ts0 = nullptr;
     uint64_t *mbits;                                     // [2][2] flagged input pixels
+    __device__ float *tsc(int b) const { return ts0 + b * TSB; }
+    __device__ __bf16 *tsh(int b) const { return (__bf16 *)(tsc(b) + 32 * CKM); }
+    __device__ __bf16 *tsl(int b) const { return tsh(b) + 32 * CKB; }
+    __device__ float *tswx(int b) const { return tsc(b) + 32 * CKM + 32 * CKB; }
+    __device__ float *tswsx(int b) const { return tswx(b) + FitShape<D>::NA * SW; }
     // buffer b (0/1) of each double-buffered table (no pointer arrays: a
     // runtime index into one would place it in scratch)
     __device__ float *cvec(int b) const { return cvec0 + b * (32 * CKM); }
@@ -46,7 +61,7 @@ struct FitLds8 {
     __device__ double *wsxd(int b) const { return wsxd0 + b * (FitShape<D>::NRA * SW); }
     __host__ __device__ static size_t bytes(int nwm) {
         using S = FitShape<D>;
-        size_t w = 2 * INP + 2 * 32 * CKM + 2 * (S::NA + S::NRA) * SW;
+        size_t w = 2 * INP + 2 * 32 * CKM + 2 * (S::NA + S::NRA) * SW + (TS ? 2 * TSB : 0);
         size_t b = w * 4 + (size_t)2 * (S::NA + S::NRA) * SW * 8 + 4 * 8;
         size_t rhs = (size_t)2 * nwm * S::NR * 32 * 8;   // end-of-kernel reuse
         return (b > rhs ? b : rhs) + 64;
@@ -63,8 +78,14 @@ struct FitLds8 {
         wxd0 = (double *)(wsx0 + 2 * S::NRA * SW);
         wsxd0 = wxd0 + 2 * S::NA * SW;
         mbits = (uint64_t *)(wsxd0 + 2 * S::NRA * SW);
+        if (TS) ts0 = (float *)(mbits + 4);             // [2][TSB] (TSB is a multiple of 4)
     }
 };
+
+// Steps of a strip: the input rows plus the rows the pipeline drains (the
+// moments of output row y run one step after its convolution, TS's two).
+template <bool TS>
+__device__ __forceinline__ int fit8_strip_steps(int rows) { return fit8_steps(rows + (TS ? 2 : 1)); }
 
 // Convolution wave cw (wave-uniform) of the NWC convolution waves, with up
 // to NP planes (from plist8 for 8 waves, plist for 4).  Wave 0 (W0) also
@@ -75,7 +96,8 @@ template <int D, int HH, int PREC, int NWC, int NP, bool W0>
 __device__ int fit_conv8(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
                          int ry1, bool active, int cw) {
     using S = FitShape<D>;
-    using L = FitLds8<D, HH>;
+    constexpr bool TS = PREC == ARGUS_BF16X3;
+    using L = FitLds8<D, HH, TS>;
     constexpr int K = L::K;
     constexpr int NR_ = K - 1 + U8;                      // window registers per plane
     const int tid = threadIdx.x, lane = tid & 63;
@@ -157,6 +179,7 @@ __device__ int fit_conv8(const FitArgs &a, float *lds, int sx_begin, int sx_end,
             }
         };
         uint32_t hist = 0;                 // bit j: input row yy-j has a flagged pixel in reach
+        bool pend = false;                 // TS: the previous step wrote an output row's c
         const int ystart = ry0 - HH;
         const int yend = active ? ry1 + HH : ystart;
         if (active) {
@@ -178,8 +201,10 @@ __device__ int fit_conv8(const FitArgs &a, float *lds, int sx_begin, int sx_end,
         // keeps the window registers free of conditional updates.
         auto step = [&](auto uc, int yy) {
             constexpr int u = decltype(uc)::value;
-            const int buf = yy & 1;
-            const bool live = yy < yend;
+            // steps start at an even row (ys0), so the buffer parity is the
+            // sub-step's: every table address is a constant offset
+            constexpr int buf = u & 1;
+            const bool live = yy >= ystart && yy < yend;
             if (live) {
                 if (yy + 1 < yend) stage(buf ^ 1);
                 if (yy + 2 < yend) fetch_in(yy + 2);
@@ -283,12 +308,46 @@ __device__ int fit_conv8(const FitArgs &a, float *lds, int sx_begin, int sx_end,
                     }
                 }
             }
+            if constexpr (TS) {
+                // split tables of the previous step's output row: this wave's
+                // four basis rows k, fixed up (c'_k = c_k + gam_k c_0; the
+                // background row is 1, rows past it stay zero), and their
+                // bf16 hi/lo parts; the last wave copies the row's weights
+                if (pend) {
+                    const int pb = buf ^ 1;
+                    const float *cv = l.cvec(pb);
+                    const float c0v = cv[lane];
+                    float *tc = l.tsc(buf);
+                    __bf16 *th = l.tsh(buf), *tl = l.tsl(buf);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = cw * 4 + q;
+                        if (k <= a.nb) {
+                            const float c = k < a.nb ? cv[k * L::CKM + lane] + uload(&a.tab->gam[k]) * c0v
+                                                     : 1.f;
+                            const __bf16 h = (__bf16)c;
+                            tc[k * L::CKM + lane] = c;
+                            th[k * L::CKB + lane] = h;
+                            tl[k * L::CKB + lane] = (__bf16)(c - (float)h);
+                        }
+                    }
+                    if (cw == NWC - 1) {
+#pragma unroll
+                        for (int e = 0; e < S::NA; ++e) l.tswx(buf)[e * SW + lane] = l.wx(pb)[e * SW + lane];
+#pragma unroll
+                        for (int e = 0; e < S::NRA; ++e) l.tswsx(buf)[e * SW + lane] = l.wsx(pb)[e * SW + lane];
+                    }
+                }
+                pend = outrow;
+            }
             __syncthreads();
         };
-        // one extra step drains the last output row into the moments; the
-        // step count is padded to whole blocks (the MFMA waves pad alike)
-        const int ylast = ystart + fit8_steps(yend - ystart + 1) - 1;
-        for (int yy = ystart; yy <= ylast; yy += U8) {
+        // extra steps drain the last output row into the moments; the step
+        // count is padded to whole blocks (the MFMA waves count alike)
+        // (an odd first row gets one leading step that only keeps the count)
+        const int ys0 = ystart & ~1;
+        const int ylast = ys0 + fit8_strip_steps<TS>(yend - ys0) - 1;
+        for (int yy = ys0; yy <= ylast; yy += U8) {
             step(std::integral_constant<int, 0>{}, yy);
             step(std::integral_constant<int, 1>{}, yy + 1);
             step(std::integral_constant<int, 2>{}, yy + 2);
@@ -303,6 +362,61 @@ __device__ int fit_conv8(const FitArgs &a, float *lds, int sx_begin, int sx_end,
     return count;
 }
 
+// TS: the moments of one row into acc from the split tables (tc: c', th/tl:
+// its hi/lo parts, wx: w xt^a).  A lane takes 8 pixels per 32-pixel step: the
+// A operands are read split; B = w xt^a c'_l is formed and split here (it
+// differs per task); the products hi*hi, hi*lo, lo*hi in that order.
+template <int MW, int STR, int NTW, int CKM, int CKB>
+__device__ __forceinline__ void row_ts_acc(const float *tc, const __bf16 *th, const __bf16 *tl,
+                                           const float *wx, int lane,
+                                           floatx4 (&acc)[NTW > 0 ? NTW : 1]) {
+    if constexpr (NTW > 0) {
+        const int col = lane & 15, pk = lane >> 4;
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < SW / 32; ++s) {
+            const int p0 = 32 * s + 8 * pk;
+            const bf16x8 h0 = *(const bf16x8 *)(th + col * CKB + p0);
+            const bf16x8 l0 = *(const bf16x8 *)(tl + col * CKB + p0);
+            const bf16x8 h1 = *(const bf16x8 *)(th + (16 + col) * CKB + p0);
+            const bf16x8 l1 = *(const bf16x8 *)(tl + (16 + col) * CKB + p0);
+            float c0[8], c1[8];
+            {
+                const float4 a0 = *(const float4 *)(tc + col * CKM + p0);
+                const float4 a1 = *(const float4 *)(tc + col * CKM + p0 + 4);
+                const float4 b0 = *(const float4 *)(tc + (16 + col) * CKM + p0);
+                const float4 b1 = *(const float4 *)(tc + (16 + col) * CKM + p0 + 4);
+                c0[0] = a0.x; c0[1] = a0.y; c0[2] = a0.z; c0[3] = a0.w;
+                c0[4] = a1.x; c0[5] = a1.y; c0[6] = a1.z; c0[7] = a1.w;
+                c1[0] = b0.x; c1[1] = b0.y; c1[2] = b0.z; c1[3] = b0.w;
+                c1[4] = b1.x; c1[5] = b1.y; c1[6] = b1.z; c1[7] = b1.w;
+            }
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                const int t = MW + STR * j;
+                const int a = t / 3, bp = t % 3;
+                const float4 w0 = *(const float4 *)(wx + a * SW + p0);
+                const float4 w1 = *(const float4 *)(wx + a * SW + p0 + 4);
+                const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+                bf16x8 bh, bl;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float B = wv[e] * ((bp == 0) ? c0[e] : c1[e]);
+                    const __bf16 bb = (__bf16)B;
+                    bh[e] = bb;
+                    bl[e] = (__bf16)(B - (float)bb);
+                }
+                const bf16x8 ah = (bp == 2) ? h1 : h0;
+                const bf16x8 al = (bp == 2) ? l1 : l0;
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
+            }
+        }
+    }
+}
+
 // MFMA wave W (NWC <= W < NWC + NWM) of the workgroup: the moments of the
 // previous output row from the tables the convolution waves wrote, and the
 // right-hand-side pieces of its pixels.
@@ -310,7 +424,8 @@ template <int D, int HH, int W, int PREC, int NWC, int NWM>
 __device__ void fit_mfma8(const FitArgs &a, float *lds, int sx_begin, int sx_end, int ry0,
                           int ry1, bool active, double *part) {
     using S = FitShape<D>;
-    using L = FitLds8<D, HH>;
+    constexpr bool TS = PREC == ARGUS_BF16X3;
+    using L = FitLds8<D, HH, TS>;
     constexpr int MW = W - NWC;
     constexpr int PXW = SW / NWM, PXH = PXW / 2;         // rhs pixels per wave and half-wave
     const int tid = threadIdx.x, lane = tid & 63;
@@ -345,10 +460,57 @@ __device__ void fit_mfma8(const FitArgs &a, float *lds, int sx_begin, int sx_end
     for (int strip = 0; strip < nstrips; ++strip) {
         const int ystart = ry0 - HH;
         const int yend = active ? ry1 + HH : ystart;
-        const int ylast = ystart + fit8_steps(yend - ystart + 1) - 1;
+        const int ys0 = ystart & ~1;                 // the convolution waves' first step
+        const int ylast = ys0 + fit8_strip_steps<TS>(yend - ys0) - 1;
         __syncthreads();
-        for (int yy = ystart; yy <= ylast; ++yy) {
+        for (int yy = ys0; yy <= ylast; ++yy) {
             const int buf = yy & 1;
+            if constexpr (TS) {
+                // moments of output row y = yy - 2 - h: its c was convolved two
+                // steps ago and its split tables built in the previous step
+                const int y = yy - 2 - HH;
+                if (yy - 2 >= ry0 + HH && yy - 2 < yend) {
+                    const int pb = buf ^ 1;
+                    double ypw[2 * D + 1];
+                    if constexpr (DEFER) {
+                        if (have) {
+                            ypowers(yprev, ypw);
+                            gram.flush(acc, ypw);
+                        }
+                    }
+                    ypowers(y, ypw);
+                    if constexpr (!DEFER) {
+                        row_ts_acc<MW, NWM, G::NTW, L::CKM, L::CKB>(l.tsc(pb), l.tsh(pb), l.tsl(pb),
+                                                                     l.tswx(pb), lane, acc);
+                        gram.flush(acc, ypw);
+                    }
+                    // rhs pieces of this half-wave's pixels: w s xt^e c'_k
+                    const int k = lane & 31, half = lane >> 5;
+                    float ra[S::NRA];
+#pragma unroll
+                    for (int e = 0; e < S::NRA; ++e) ra[e] = 0.f;
+#pragma unroll
+                    for (int i = 0; i < PXH; ++i) {
+                        const int px = MW * PXW + half * PXH + i;
+                        const float c = l.tsc(pb)[k * L::CKM + px];
+#pragma unroll
+                        for (int e = 0; e < S::NRA; ++e) ra[e] += l.tswsx(pb)[e * SW + px] * c;
+                    }
+#pragma unroll
+                    for (int e = 0; e < S::NRA; ++e)
+#pragma unroll
+                        for (int b = 0; b <= D; ++b)
+                            if (e + b <= D) RF[qidx(e, b, D)] += ypw[b] * (double)ra[e];
+                    if constexpr (DEFER) {
+                        row_ts_acc<MW, NWM, G::NTW, L::CKM, L::CKB>(l.tsc(pb), l.tsh(pb), l.tsl(pb),
+                                                                     l.tswx(pb), lane, acc);
+                        have = true;
+                        yprev = y;
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
             // moments of output row y = yy - 1 - h, written during the previous step
             const int y = yy - 1 - HH;
             if (yy - 1 >= ry0 + HH && yy - 1 < yend) {
@@ -454,11 +616,27 @@ __global__ __launch_bounds__(64 * (NWC + NWM)) void fit_accum8_kernel(FitArgs a)
     const bool active = sx0 < sx1 && ry0 < ry1;    // otherwise the partial is all zeros
     const int pid = ((ry * a.RX + rx) * a.rchunks + rc) * a.spt + s;
     double *part = a.partials + (size_t)pid * a.stride;
-    // constant tail of c: 1 at index nb (background), zeros after, both buffers
-    FitLds8<D, HH> L(lds);
-    for (int i = tid; i < 2 * 32 * FitLds8<D, HH>::CKM; i += NTH) {
-        const int k = (i / FitLds8<D, HH>::CKM) % 32;
+    // constant tail of c: 1 at index nb (background), zeros after, both
+    // buffers; with split tables (BF16x3) their rows past nb are zero too
+    constexpr bool TS = PREC == ARGUS_BF16X3;
+    using LT = FitLds8<D, HH, TS>;
+    LT L(lds);
+    for (int i = tid; i < 2 * 32 * LT::CKM; i += NTH) {
+        const int k = (i / LT::CKM) % 32;
         if (k >= a.nb) L.cvec0[i] = (k == a.nb) ? 1.f : 0.f;
+    }
+    if constexpr (TS) {
+        for (int i = tid; i < 2 * 32 * LT::CKM; i += NTH) {
+            const int b = i / (32 * LT::CKM), k = (i / LT::CKM) % 32;
+            if (k > a.nb) L.tsc(b)[i % (32 * LT::CKM)] = 0.f;
+        }
+        for (int i = tid; i < 2 * 32 * LT::CKB; i += NTH) {
+            const int b = i / (32 * LT::CKB), k = (i / LT::CKB) % 32, r = i % (32 * LT::CKB);
+            if (k > a.nb) {
+                L.tsh(b)[r] = (__bf16)0.f;
+                L.tsl(b)[r] = (__bf16)0.f;
+            }
+        }
     }
     int count = 0;
     if (w == 0)
@@ -495,7 +673,7 @@ int fit_accum8_launch(argus_ctx *ctx, const FitArgs &fa, int D, dim3 grid) {
     bool ok = false;
 #define ARGUS_FH(DD, HH)                                                                   \
     if (D == DD && fa.h == HH) {                                                           \
-        size_t lds = FitLds8<DD, HH>::bytes(NWM);                                          \
+        size_t lds = FitLds8<DD, HH, PREC == ARGUS_BF16X3>::bytes(NWM);                    \
         err = hipFuncSetAttribute((const void *)fit_accum8_kernel<DD, HH, PREC, NWC, NWM>, \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (err == hipSuccess)                                                             \
