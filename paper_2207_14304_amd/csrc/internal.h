@@ -80,6 +80,18 @@ __device__ __forceinline__ void gst(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
 }
 
+// Workgroup b of a launch of n runs on XCD b % 8 of the 8 (the dispatcher
+// deals workgroups round-robin over the XCDs, each with its own L2).  This
+// returns the logical block that b stands for so that every XCD takes one
+// contiguous range of logical blocks: neighbouring tiles of a raster order
+// (which share halo rows) then share an L2 and run close in time.
+constexpr int ARGUS_NXCD = 8;
+__device__ __forceinline__ int argus_xcd_block(int b, int n) {
+    const int q = n / ARGUS_NXCD, r = n % ARGUS_NXCD;
+    const int x = b % ARGUS_NXCD, i = b / ARGUS_NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // ---- helpers implemented in argus.hip --------------------------------------
 int argus_fail(argus_ctx *ctx, int code, const char *fmt, ...);
 int argus_ws_reserve(argus_ctx *ctx, size_t bytes);

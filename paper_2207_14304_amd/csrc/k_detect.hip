@@ -69,7 +69,10 @@ __device__ __forceinline__ float snr_of(float D, float V, uint32_t m) {
 template <bool SRC>
 __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
     __shared__ __align__(16) float s[ROWS + 2][LW];
-    const int sx = blockIdx.x, y0 = blockIdx.y * ROWS, tid = threadIdx.x;
+    // tiles in raster order, each XCD a contiguous band of them (the halo rows
+    // a tile shares with the tiles above and below stay in one L2)
+    const int lb = argus_xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int sx = lb % a.nsx, y0 = (lb / a.nsx) * ROWS, tid = threadIdx.x;
     const int x0 = sx * SEG;
     const int64_t P = a.pitch;
     // SNR of rows y0-1 .. y0+ROWS, 4-pixel chunks.  Vector path: all loads of
@@ -137,13 +140,21 @@ __global__ __launch_bounds__(NTHR) void detect_map_kernel(DetArgs a) {
     for (int k = 0; k < ROWS / 4; ++k) {
         const int rr = w + 4 * k, y = y0 + rr;
         if (y >= a.H) break;                       // uniform across the wave
+        // a lane's 4 pixels as one 16-byte read (consecutive lanes, no bank
+        // conflicts), the neighbours from the adjacent lanes, the strip's two
+        // edge values by broadcast reads
+        auto row6 = [&](int r, float (&v)[6]) {
+            const float4 c4 = *(const float4 *)&s[r][4 + 4 * lane];
+            const float le = s[r][3], re = s[r][4 + SEG];
+            const float l = __shfl_up(c4.w, 1), rt = __shfl_down(c4.x, 1);
+            v[0] = lane == 0 ? le : l;
+            v[1] = c4.x; v[2] = c4.y; v[3] = c4.z; v[4] = c4.w;
+            v[5] = lane == 63 ? re : rt;
+        };
         float up[6], md[6], dn[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            up[j] = s[rr][3 + 4 * lane + j];
-            md[j] = s[rr + 1][3 + 4 * lane + j];
-            dn[j] = s[rr + 2][3 + 4 * lane + j];
-        }
+        row6(rr, up);
+        row6(rr + 1, md);
+        row6(rr + 2, dn);
         float outs[4];
         uint32_t outd = 0;
         int cnt = 0;
@@ -350,7 +361,7 @@ int launch_detect_any(argus_ctx *ctx, argus_dims d, const float *diff, const flo
     a.tile_sum = w + 2 * (size_t)a.nseg;
     a.tile_off = a.tile_sum + a.ntile;
     argus_time_begin(ctx);
-    const dim3 mg(a.nsx, (d.height + ROWS - 1) / ROWS);
+    const dim3 mg(a.nsx * ((d.height + ROWS - 1) / ROWS));
     if (src)
         hipLaunchKernelGGL(detect_map_kernel<true>, mg, dim3(NTHR), 0, ctx->stream, a);
     else
