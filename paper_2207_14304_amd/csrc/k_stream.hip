@@ -23,15 +23,17 @@ struct CalArgs {
 };
 
 // cal = (raw - dark)/flat, var = (max(raw - dark, 0)/g + rn^2/g^2)/flat^2,
-// evaluated in FP64 and rounded once to FP32.  raw - dark is exact in FP64
-// (raw is an integer below 2^16, dark a float); the division by the flat is a
-// multiplication by its FP64 reciprocal, computed once per pixel (and shared
-// by every frame of a fused calibration), which is within one FP64 ulp of the
-// quotient (the FP32 results are those of the quotient except where it lies
-// within an FP64 ulp of an FP32 rounding boundary).
+// evaluated in FP64 and rounded once to FP32, with per-pixel constants shared
+// by every frame of a fused calibration: rf = 1/flat (the hardware estimate
+// refined by Newton steps, within one FP64 ulp), ndr = -dark rf, A = rf/g and
+// B = rn^2 rf^2 / g^2, so that
+//   cal64 = fma(raw, rf, ndr),   var64 = fma(max(cal64, 0), A, B)
+// (max(raw - dark, 0) rf = max(cal, 0) as rf > 0).  cal64 is within a few
+// FP64 ulps of max(|raw rf|, |dark rf|) of the quotient, var64 within a few
+// ulps: the FP32 results are those of the exact expressions except where
+// these lie that close to an FP32 rounding boundary.
 struct CalPix {
-    double rf, rf2;            // 1 / flat, its square
-    double d;
+    double rf, ndr, A, B;
     bool bad;
 };
 
@@ -45,21 +47,26 @@ __device__ __forceinline__ double rcp64(double x) {
     return __builtin_fma(r, e, r);
 }
 
-__device__ __forceinline__ CalPix cal_pix(float d, float f, uint8_t b) {
+__device__ __forceinline__ CalPix cal_pix(const CalArgs &a, float d, float f, uint8_t b) {
     CalPix p;
     p.bad = (b != 0) || !(f > 0.f) || !__builtin_isfinite(f) || !__builtin_isfinite(d);
     // a BAD pixel's values are discarded: any positive operand will do
     p.rf = rcp64(p.bad ? 1.0 : (double)f);
-    p.rf2 = p.rf * p.rf;
-    p.d = (double)d;
+    p.ndr = -(double)d * p.rf;
+    p.A = a.inv_g * p.rf;
+    p.B = a.rn2_g2 * (p.rf * p.rf);
     return p;
+}
+
+__device__ __forceinline__ void cal_val64(uint32_t r, const CalPix &p, double &cd, double &vd) {
+    cd = __builtin_fma((double)r, p.rf, p.ndr);
+    vd = __builtin_fma(fmax(cd, 0.0), p.A, p.B);
 }
 
 __device__ __forceinline__ void cal_one(const CalArgs &a, uint16_t r, const CalPix &p, float &c,
                                         float &v, uint8_t &m) {
-    double sig = (double)r - p.d;
-    double cd = sig * p.rf;
-    double vd = (fmax(sig, 0.0) * a.inv_g + a.rn2_g2) * p.rf2;
+    double cd, vd;
+    cal_val64(r, p, cd, vd);
     c = p.bad ? 0.f : (float)cd;
     v = p.bad ? 0.f : (float)vd;
     m = (p.bad ? ARGUS_BAD : 0u) | ((float)r >= a.sat ? ARGUS_SAT : 0u);
@@ -87,7 +94,7 @@ __global__ __launch_bounds__(256) void calibrate_kernel(CalArgs a) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             uint8_t b = (uint8_t)(((i < 4 ? b8.x : b8.y) >> (8 * (i & 3))) & 0xff);
-            cal_one(a, r[i], cal_pix(d[i], f[i], b), c[i], v[i], m[i]);
+            cal_one(a, r[i], cal_pix(a, d[i], f[i], b), c[i], v[i], m[i]);
         }
         *(float4 *)(a.cal + o) = make_float4(c[0], c[1], c[2], c[3]);
         *(float4 *)(a.cal + o + 4) = make_float4(c[4], c[5], c[6], c[7]);
@@ -105,7 +112,7 @@ __global__ __launch_bounds__(256) void calibrate_kernel(CalArgs a) {
     for (int i = 0; i < n; ++i) {
         float c, v;
         uint8_t m;
-        cal_one(a, a.raw[o + i], cal_pix(a.dark[o + i], a.flat[o + i], a.bpm ? a.bpm[o + i] : 0), c, v, m);
+        cal_one(a, a.raw[o + i], cal_pix(a, a.dark[o + i], a.flat[o + i], a.bpm ? a.bpm[o + i] : 0), c, v, m);
         a.cal[o + i] = c;
         if (a.var) a.var[o + i] = v;
         a.mask[o + i] = m;
@@ -318,11 +325,11 @@ __device__ __forceinline__ void sort_keys(uint32_t (&k)[N]) {
 }
 
 // the arithmetic of cal_one without the mask
-__device__ __forceinline__ void cal_val(const CalArgs &a, uint32_t r, const CalPix &p, float &c,
-                                        float &v) {
-    const double sig = (double)r - p.d;
-    c = (float)(sig * p.rf);
-    v = (float)((fmax(sig, 0.0) * a.inv_g + a.rn2_g2) * p.rf2);
+__device__ __forceinline__ void cal_val(uint32_t r, const CalPix &p, float &c, float &v) {
+    double cd, vd;
+    cal_val64(r, p, cd, vd);
+    c = (float)cd;
+    v = (float)vd;
 }
 
 template <int N>
@@ -347,7 +354,7 @@ __device__ __forceinline__ void calcoadd_one(const CalCoaddArgs &a, const uint16
     double xd[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        cal_val(a.cal, key[k] >> 3, cp, x[k], v[k]);
+        cal_val(key[k] >> 3, cp, x[k], v[k]);
         xd[k] = (double)x[k];
     }
     int l = 0, h = nv - 1;
@@ -439,14 +446,14 @@ __global__ __launch_bounds__(256) void calcoadd_kernel(CalCoaddArgs a) {
             r[3][i] = (uint16_t)(r4.y >> 16);
         }
 #pragma unroll
-        for (int p = 0; p < CO_PX; ++p) cp[p] = cal_pix(d[p], f[p], (uint8_t)(b4 >> (8 * p)));
+        for (int p = 0; p < CO_PX; ++p) cp[p] = cal_pix(a.cal, d[p], f[p], (uint8_t)(b4 >> (8 * p)));
     } else {
 #pragma unroll
         for (int p = 0; p < CO_PX; ++p) {
             const bool in = p < n;
             const float d = in ? a.cal.dark[o + p] : 0.f, f = in ? a.cal.flat[o + p] : 1.f;
             const uint8_t b = in && a.cal.bpm ? a.cal.bpm[o + p] : 0;
-            cp[p] = cal_pix(d, f, b);
+            cp[p] = cal_pix(a.cal, d, f, b);
 #pragma unroll
             for (int i = 0; i < N; ++i) r[p][i] = in ? a.raw[i][o + p] : (uint16_t)0;
         }
