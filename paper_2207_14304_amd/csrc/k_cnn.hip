@@ -68,8 +68,14 @@ struct ConvShape {
     static constexpr int ACT = (PW * PW * CIN + 7) & ~7;
 };
 
+// forward (MODE 0) on 4-wave workgroups, the backward-data pass (MODE 1,
+// with its gate loads) on 8 waves: the faster of the two for each
+template <int MODE>
+constexpr int conv_threads() { return MODE == 0 ? 256 : CT; }
+
 template <int CIN, int MODE>
-__global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs a) {
+    constexpr int CTM = conv_threads<MODE>();
     using CS = ConvShape<CIN>;
     constexpr int KP = CS::KP, KS = CS::KS, W = 31, PW = CS::PW;
     extern __shared__ __align__(16) bf16 sm[];
@@ -87,7 +93,7 @@ __global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
         B0[ks] = *(const bf16x8 *)&a.w[(2 * col) * KP + ks * 32 + 8 * g];
         B1[ks] = *(const bf16x8 *)&a.w[(2 * col + 1) * KP + ks * 32 + 8 * g];
     }
-    for (int i = tid; i < CS::ACT / 8; i += CT) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < CS::ACT / 8; i += CTM) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const bf16 *src = a.in + (size_t)s * a.npx * CIN;
     if constexpr (CIN % 8 == 0) {
@@ -96,16 +102,16 @@ __global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
         constexpr int C8 = CIN / 8, U = 8;
         const int n8 = a.npx * C8;
         const uint4 *src4 = (const uint4 *)src;
-        for (int i0 = tid; i0 < n8; i0 += CT * U) {
+        for (int i0 = tid; i0 < n8; i0 += CTM * U) {
             uint4 v[U];
 #pragma unroll
             for (int e = 0; e < U; ++e) {
-                const int i = i0 + e * CT;
+                const int i = i0 + e * CTM;
                 v[e] = i < n8 ? src4[i] : make_uint4(0u, 0u, 0u, 0u);
             }
 #pragma unroll
             for (int e = 0; e < U; ++e) {
-                const int i = i0 + e * CT;
+                const int i = i0 + e * CTM;
                 if (i < n8) {
                     const int p = i / C8, c8 = i % C8, y = p / W, x = p % W;
                     *(uint4 *)&act[((y + 1) * PW + (x + 1)) * CIN + 8 * c8] = v[e];
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
             }
         }
     } else {
-        for (int i = tid; i < a.npx * CIN; i += CT) {
+        for (int i = tid; i < a.npx * CIN; i += CTM) {
             int p = i / CIN, c = i % CIN;
             int y = p / W, x = p % W;
             act[((y + 1) * PW + (x + 1)) * CIN + c] = src[i];
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(CT) void cnn_conv_kernel(ConvArgs a) {
         }
     };
     // two tiles per pass (t and t + NW): four independent accumulator chains
-    constexpr int NW = CT / 64;
+    constexpr int NW = CTM / 64;
     const int ntile = (a.npx + 15) / 16;
     for (int t = wave; t < ntile; t += 2 * NW) {
         const bool two = t + NW < ntile;                // uniform across the wave
@@ -916,7 +922,8 @@ int conv_launch(argus_ctx *ctx, const ConvArgs &ca) {
     size_t lds = (size_t)ConvShape<CIN>::ACT * sizeof(bf16);
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_conv_kernel<CIN, MODE>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n), dim3(CT), lds, ctx->stream, ca);
+    hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n), dim3(conv_threads<MODE>()), lds,
+                       ctx->stream, ca);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
