@@ -357,6 +357,9 @@ def surrogate_leg(args, torch, argus):
     cnn = argus.CNN(ctx, max_tiles=64)
     cnn.set_weights(sur.init_weights(1))
     n = X.shape[0]
+    # the kernels run only on a tile's valid stamps (the rest of its 64 slots
+    # are skipped), so the work is counted on those
+    stamps_per_sample = float(V.float().sum(1).mean())
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -369,8 +372,11 @@ def surrogate_leg(args, torch, argus):
     torch.cuda.synchronize()
     train_ms = e0.elapsed_time(e1)
     samples_s = steps * 32 / (train_ms / 1e3)
-    # 3 x 1.74 GMAC per training sample (forward, data and weight gradients)
-    train_tflops = samples_s * 3 * 1.74e9 * 2 / 1e12
+    # MACs per valid stamp (961 px, 32 output channels): forward 18 + 3 x 288
+    # per pixel and channel, the same again for the weight gradients, and
+    # 3 x 288 for the data gradients of layers 3..1
+    mac_stamp = 961 * 32 * (2 * (18 + 3 * 288) + 3 * 288)
+    train_tflops = samples_s * stamps_per_sample * mac_stamp * 2 / 1e12
     cnn.set_weights(sur.fold_standardization(cnn.get_weights(), mu.cpu().numpy(),
                                              sd.cpu().numpy()))
     del X, V, T, Ts
@@ -415,6 +421,8 @@ def surrogate_leg(args, torch, argus):
     med = lambda k: float(np.nanmedian([r[k] for r in ok]))
     res = {"train": {"samples": n, "frames": args.sur_frames, "epochs": args.sur_epochs,
                      "generate_s": round(t_gen, 2), "samples_per_s": round(samples_s, 1),
+                     "valid_stamps_per_sample": round(stamps_per_sample, 2),
+                     "stamps_per_s": round(samples_s * stamps_per_sample, 0),
                      "TFLOP/s_bf16": round(train_tflops, 1),
                      "frac_bf16_peak": round(train_tflops / 2500.0, 4)},
            "plain_per_tile_mpix_s": round(W * H / (ms_plain / 1e3) / 1e6, 1),

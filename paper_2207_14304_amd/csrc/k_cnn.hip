@@ -42,48 +42,52 @@ struct argus_cnn {
 namespace {
 
 constexpr int NT = 256;
-constexpr int CT = 512;        // convolution workgroups: 8 waves
 constexpr int WT = 1024;       // weight-gradient workgroups (one per CU by LDS): 16 waves
 
 __device__ __forceinline__ float bf2f(bf16 x) { return (float)x; }
 
 // ---------------------------------------------------------------------------
-// Convolution: one workgroup per stamp; 61 output tiles of 16 pixels x 32
-// channels spread over the 8 waves; K = 9 * CIN (padded to 32) per tile.
-// The weight fragments of every K step stay in registers for the whole
-// stamp (loaded once from global memory), so the tile loop reads only the
-// activations from LDS, and two workgroups fit a CU.
+// Convolution: two workgroups per stamp, one per band of output rows (0..15
+// and 16..30: 31 and 30 output tiles of 16 raster pixels x 32 channels
+// spread over the waves); K = 9 * CIN (padded to 32) per tile.  A band holds
+// its 18 input rows (with the halo) in LDS, so four workgroups fit a CU.  The
+// weight fragments of every K step stay in registers (loaded once from global
+// memory), so the tile loop reads only the activations from LDS.
 // MODE 0: z + bias, ReLU.  MODE 1: gate by (g > 0) (backward data).
 struct ConvArgs {
     const bf16 *in, *w, *gate;
     const float *bias;
-    const int32_t *order, *nvalid;              // workgroup b < *nvalid takes stamp order[b]
+    const int32_t *order, *nvalid;              // workgroup b < 2 *nvalid: stamp order[b / 2], band b % 2
     bf16 *out;
+    float *pool;                                // forward: per stamp and band channel sums of out, or null
     int npx, n;                                 // pixels per stamp (961), stamps
 };
 
 template <int CIN>
 struct ConvShape {
     static constexpr int KP = ((9 * CIN + 31) / 32) * 32, KS = KP / 32, PW = 33;
-    static constexpr int ACT = (PW * PW * CIN + 7) & ~7;
+    static constexpr int BAND = 16, NBAND = 2;          // output rows per band, bands per stamp
+    static constexpr int AROWS = BAND + 2;              // input rows y0 - 1 .. y0 + BAND
+    static constexpr int ACT = (AROWS * PW * CIN + 7) & ~7;
 };
 
-// forward (MODE 0) on 4-wave workgroups, the backward-data pass (MODE 1,
-// with its gate loads) on 8 waves: the faster of the two for each
+// 4-wave workgroups, four per CU (LDS and registers)
 template <int MODE>
-constexpr int conv_threads() { return MODE == 0 ? 256 : CT; }
+constexpr int conv_threads() { return 256; }
 
 template <int CIN, int MODE>
-__global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(conv_threads<MODE>(), 4) void cnn_conv_kernel(ConvArgs a) {
     constexpr int CTM = conv_threads<MODE>();
     using CS = ConvShape<CIN>;
     constexpr int KP = CS::KP, KS = CS::KS, W = 31, PW = CS::PW;
     extern __shared__ __align__(16) bf16 sm[];
-    bf16 *act = sm;                             // [33][33][CIN], zero border
+    bf16 *act = sm;                             // [18][33][CIN]: rows y0 - 1 .. y0 + 16, zero border
     // the valid stamps come first in the grid (compacted order); the rest of
     // the workgroups leave at once
-    if ((int)blockIdx.x >= *a.nvalid) return;
-    const int s = a.order[blockIdx.x], tid = threadIdx.x;
+    if ((int)blockIdx.x >= *a.nvalid * CS::NBAND) return;
+    const int s = a.order[blockIdx.x / CS::NBAND], tid = threadIdx.x;
+    const int y0 = (blockIdx.x % CS::NBAND) * CS::BAND;          // first output row of the band
+    const int p0 = y0 * W, p1 = min(a.npx, p0 + CS::BAND * W);   // its pixels
     const int lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
     // B fragments: output channels 2 col (B0) and 2 col + 1 (B1), k = ks*32 +
     // 8g .. +7, so a lane's two results of a pixel are adjacent channels
@@ -95,13 +99,16 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
     }
     for (int i = tid; i < CS::ACT / 8; i += CTM) ((uint4 *)act)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
+    // the input rows of the band that lie in the stamp: pixels q0 .. q1 - 1,
+    // LDS row y - y0 + 1
+    const int q0 = max(y0 - 1, 0) * W, q1 = min(a.npx, (y0 + CS::BAND + 1) * W);
     const bf16 *src = a.in + (size_t)s * a.npx * CIN;
     if constexpr (CIN % 8 == 0) {
         // 16-byte pieces (8 channels of a pixel), eight loads in flight per
         // thread before their LDS stores
         constexpr int C8 = CIN / 8, U = 8;
-        const int n8 = a.npx * C8;
-        const uint4 *src4 = (const uint4 *)src;
+        const int n8 = (q1 - q0) * C8;
+        const uint4 *src4 = (const uint4 *)(src + (size_t)q0 * CIN);
         for (int i0 = tid; i0 < n8; i0 += CTM * U) {
             uint4 v[U];
 #pragma unroll
@@ -113,16 +120,16 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
             for (int e = 0; e < U; ++e) {
                 const int i = i0 + e * CTM;
                 if (i < n8) {
-                    const int p = i / C8, c8 = i % C8, y = p / W, x = p % W;
-                    *(uint4 *)&act[((y + 1) * PW + (x + 1)) * CIN + 8 * c8] = v[e];
+                    const int p = q0 + i / C8, c8 = i % C8, y = p / W, x = p % W;
+                    *(uint4 *)&act[((y - y0 + 1) * PW + (x + 1)) * CIN + 8 * c8] = v[e];
                 }
             }
         }
     } else {
-        for (int i = tid; i < a.npx * CIN; i += CTM) {
+        for (int i = q0 * CIN + tid; i < q1 * CIN; i += CTM) {
             int p = i / CIN, c = i % CIN;
             int y = p / W, x = p % W;
-            act[((y + 1) * PW + (x + 1)) * CIN + c] = src[i];
+            act[((y - y0 + 1) * PW + (x + 1)) * CIN + c] = src[i];
         }
     }
     __syncthreads();
@@ -130,8 +137,8 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
     // A operand of tile t, step ks: pixel t*16 + col, inputs k = ks*32 + 8g .. +7
     auto load_a = [&](int t, int ks) -> bf16x8 {
         bf16x8 A;
-        const int p = t * 16 + col, y = p / W, x = p % W;
-        const bool pin = p < a.npx;
+        const int p = p0 + t * 16 + col, y = p / W - y0, x = p % W;
+        const bool pin = p < p1;
         if constexpr (CIN == 32) {
             const int dy = ks / 3 - 1, dx = ks % 3 - 1;
             if (pin) {
@@ -159,14 +166,15 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
     auto load_gate = [&](int t, uint32_t (&gw)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int pp = t * 16 + 4 * g + r;
-            gw[r] = (MODE == 1 && pp < a.npx)
+            const int pp = p0 + t * 16 + 4 * g + r;
+            gw[r] = (MODE == 1 && pp < p1)
                         ? *(const uint32_t *)&a.gate[((size_t)s * a.npx + pp) * 32 + 2 * col]
                         : 0u;
         }
     };
     // pixels 4g .. 4g+3 of tile t, channels 2 col and 2 col + 1: one 4-byte
     // store per pixel
+    float ps0 = 0.f, ps1 = 0.f;                 // channel sums of the stored outputs (forward)
     auto store = [&](int t, const floatx4 &r0, const floatx4 &r1, const uint32_t (&gw)[4]) {
         float b0 = 0.f, b1 = 0.f;
         if (MODE == 0) {
@@ -175,8 +183,8 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int pp = t * 16 + 4 * g + r;
-            if (pp >= a.npx) continue;
+            const int pp = p0 + t * 16 + 4 * g + r;
+            if (pp >= p1) continue;
             float v0 = r0[r], v1 = r1[r];
             if (MODE == 0) {
                 v0 = fmaxf(v0 + b0, 0.f);
@@ -188,11 +196,15 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
             }
             const bf16 o2[2] = {(bf16)v0, (bf16)v1};
             *(uint32_t *)&dst[(size_t)pp * 32 + 2 * col] = *(const uint32_t *)o2;
+            if (MODE == 0) {
+                ps0 += bf2f(o2[0]);
+                ps1 += bf2f(o2[1]);
+            }
         }
     };
     // two tiles per pass (t and t + NW): four independent accumulator chains
     constexpr int NW = CTM / 64;
-    const int ntile = (a.npx + 15) / 16;
+    const int ntile = (p1 - p0 + 15) / 16;
     for (int t = wave; t < ntile; t += 2 * NW) {
         const bool two = t + NW < ntile;                // uniform across the wave
         uint32_t g0[4], g1[4];
@@ -213,57 +225,62 @@ __global__ __launch_bounds__(conv_threads<MODE>()) void cnn_conv_kernel(ConvArgs
         store(t, p0, p1, g0);
         if (two) store(t + NW, q0, q1, g1);
     }
+    if (MODE == 0 && a.pool) {
+        // the spatial sum of the band (the head's pooling, fused): lanes col,
+        // col + 16, col + 32, col + 48 hold the same two channels, then the
+        // waves are added in order through LDS
+        ps0 += __shfl_xor(ps0, 16);
+        ps0 += __shfl_xor(ps0, 32);
+        ps1 += __shfl_xor(ps1, 16);
+        ps1 += __shfl_xor(ps1, 32);
+        float *red = (float *)sm;               // [NW][32], after every wave is done with act
+        __syncthreads();
+        if (g == 0) {
+            red[wave * 32 + 2 * col] = ps0;
+            red[wave * 32 + 2 * col + 1] = ps1;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            float sum = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) sum += red[w * 32 + tid];
+            a.pool[((size_t)s * CS::NBAND + blockIdx.x % CS::NBAND) * 32 + tid] = sum;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradients: G workgroups per tile, workgroup g taking stamps g,
-// g + G, ... of its tile (the k range).  dW[o][tap][c] = sum_p dZ[p][o]
-// A_in[p + off(tap)][c]; db[o] = sum_p dZ[p][o], as one more MFMA tile whose
-// B operand is all ones.  K steps are image rows (32 columns, the last one
-// zero).  The T G partials are summed afterwards in a fixed order.
-constexpr int WG_GROUPS = 8;
+// Weight gradients: dW[o][tap][c] = sum_p dZ[p][o] A_in[p + off(tap)][c] and
+// db[o] = sum_p dZ[p][o] (one more MFMA tile whose B operand is all ones),
+// summed over every valid stamp of the batch.  Workgroup b takes entries b,
+// b + grid, ... of the compacted list of valid stamps, so the work is even
+// whatever the tiles' fill; the per-workgroup partials are summed afterwards
+// in a fixed order.  K steps are image rows (32 columns, the last one zero).
+constexpr int WG_GROUPS = 16;   // weight-gradient workgroups per tile of the batch
 
 struct WgradArgs {
     const bf16 *dz, *ain;
-    const uint8_t *valid;
-    float *part;                                // [tiles * G][32 * 9 * CIN + 32]
-    int S, npx, G;
+    const int32_t *order, *nvalid;              // the batch's valid stamps, their count
+    float *part;                                // [workgroups][32 * 9 * CIN + 32]
+    int npx;
 };
 
-template <int CIN>
-struct WgradShape {
-    static constexpr int NJ = 9 * CIN, NTL = (NJ + 15) / 16, W = 31, DW = 32, AH = 33;
-    // input rows: x' = x + 1 in a 40-element (80-byte) row, so every 8-pixel
-    // operand is one or two aligned 16-byte reads
-    static constexpr int AW = 40;
+// The first layer (2 input channels, 18 weight columns plus the bias) is
+// bound by staging its dZ: one workgroup holds a whole stamp (69 KB, two
+// per CU), and three of its 16 waves run the MFMAs.
+struct Wg2 {
+    static constexpr int CIN = 2, NJ = 9 * CIN, NTL = (NJ + 15) / 16, W = 31, DW = 32, AH = 33, AW = 40;
     static constexpr size_t bytes() { return ((size_t)32 * W * DW + (size_t)CIN * AH * AW) * 2; }
 };
 
-// 8 bf16 starting e elements (0, 1 or 2) past a 16-byte aligned address
-__device__ __forceinline__ bf16x8 shifted8(const bf16 *p, int e) {
-    const uint4 lo = *(const uint4 *)p;
-    if (e == 0) return *(const bf16x8 *)&lo;
-    const uint4 hi = *(const uint4 *)(p + 8);
-    uint4 r;
-    if (e == 2) {
-        r = make_uint4(lo.y, lo.z, lo.w, hi.x);
-    } else {
-        r.x = __builtin_amdgcn_alignbyte(lo.y, lo.x, 2);
-        r.y = __builtin_amdgcn_alignbyte(lo.z, lo.y, 2);
-        r.z = __builtin_amdgcn_alignbyte(lo.w, lo.z, 2);
-        r.w = __builtin_amdgcn_alignbyte(hi.x, lo.w, 2);
-    }
-    return *(const bf16x8 *)&r;
-}
-
-template <int CIN>
-__global__ __launch_bounds__(WT) void cnn_wgrad_kernel(WgradArgs a) {
-    using WS = WgradShape<CIN>;
-    constexpr int NJ = WS::NJ, NTL = WS::NTL, W = WS::W, DW = WS::DW, AW = WS::AW, AH = WS::AH;
+__global__ __launch_bounds__(WT) void cnn_wgrad2_kernel(WgradArgs a) {
+    using WS = Wg2;
+    constexpr int CIN = WS::CIN, NJ = WS::NJ, NTL = WS::NTL, W = WS::W, DW = WS::DW, AW = WS::AW,
+                  AH = WS::AH;
     extern __shared__ __align__(16) bf16 sm[];
     bf16 *dzl = sm;                             // [32][31][32]   channel-first dZ
-    bf16 *al = sm + 32 * W * DW;                // [CIN][33][40]  channel-first input
-    const int b = blockIdx.x, t = b / a.G, gi = b % a.G;
+    bf16 *al = sm + 32 * W * DW;                // [CIN][33][40]  channel-first input, x' = x + 1
+    const int b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, g = lane >> 4;
     constexpr int NWV = WT / 64, NMAX = (NTL + 1 + NWV - 1) / NWV;   // weight tiles and the bias tile
@@ -275,52 +292,36 @@ __global__ __launch_bounds__(WT) void cnn_wgrad_kernel(WgradArgs a) {
     for (int i = tid; i < 32 * W * DW / 8; i += WT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = tid; i < CIN * AH * AW / 8; i += WT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    for (int s = gi; s < a.S; s += a.G) {
-        const int n = t * a.S + s;
-        if (!a.valid[n]) continue;                       // uniform across the block
+    const int nv = *a.nvalid;
+    for (int k = b; k < nv; k += gridDim.x) {
+        const int n = a.order[k];
         const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
         const bf16 *as = a.ain + (size_t)n * a.npx * CIN;
-        // a thread takes a pair of horizontally adjacent pixels (every
+        // dZ: a thread takes a pair of horizontally adjacent pixels (every
         // channel: 16-byte loads) and writes each channel's pair as one
-        // 4-byte word of the channel-first tiles; for one channel the lanes of
-        // a wave write consecutive words (no bank conflicts).  dZ pairs are
-        // x = (2m, 2m+1), the input's x = (2m-1, 2m) (its tile is shifted by
-        // the zero border); pixels outside the stamp read as zero.
-        auto load32 = [&](const bf16 *base, int y, int x, uint4 (&v)[4]) {
-            const bool in = x >= 0 && x < W;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                v[q] = in ? ((const uint4 *)(base + (size_t)(y * W + x) * 32))[q] : make_uint4(0u, 0u, 0u, 0u);
-        };
-        auto pack = [](const uint4 (&a)[4], const uint4 (&b)[4], int o) -> uint32_t {
-            const uint32_t wa = (&a[o >> 3].x)[(o >> 1) & 3], wb = (&b[o >> 3].x)[(o >> 1) & 3];
-            return (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
-        };
+        // 4-byte word of the channel-first tile; for one channel the lanes of
+        // a wave write consecutive words (no bank conflicts).  x = 31 reads
+        // as zero.
         constexpr int NPAIR = W * 16;                    // 31 rows x 16 pairs
         for (int q0 = tid; q0 < NPAIR; q0 += WT) {
             const int y = q0 / 16, m = q0 % 16;
             uint4 v0[4], v1[4];
-            load32(dzs, y, 2 * m, v0);
-            load32(dzs, y, 2 * m + 1, v1);
 #pragma unroll
-            for (int o = 0; o < 32; ++o)
-                *(uint32_t *)&dzl[(o * W + y) * DW + 2 * m] = pack(v0, v1, o);
+            for (int q = 0; q < 4; ++q) {
+                v0[q] = ((const uint4 *)(dzs + (size_t)(y * W + 2 * m) * 32))[q];
+                v1[q] = 2 * m + 1 < W ? ((const uint4 *)(dzs + (size_t)(y * W + 2 * m + 1) * 32))[q]
+                                      : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int o = 0; o < 32; ++o) {
+                const uint32_t wa = (&v0[o >> 3].x)[(o >> 1) & 3], wb = (&v1[o >> 3].x)[(o >> 1) & 3];
+                *(uint32_t *)&dzl[(o * W + y) * DW + 2 * m] =
+                    (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
+            }
         }
-        if constexpr (CIN == 32) {
-            for (int q0 = tid; q0 < NPAIR; q0 += WT) {
-                const int y = q0 / 16, m = q0 % 16;
-                uint4 v0[4], v1[4];
-                load32(as, y, 2 * m - 1, v0);
-                load32(as, y, 2 * m, v1);
-#pragma unroll
-                for (int c = 0; c < 32; ++c)
-                    *(uint32_t *)&al[(c * AH + y + 1) * AW + 2 * m] = pack(v0, v1, c);
-            }
-        } else {
-            for (int i = tid; i < a.npx * CIN; i += WT) {
-                int p = i / CIN, c = i % CIN;
-                al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
-            }
+        for (int i = tid; i < a.npx * CIN; i += WT) {
+            int p = i / CIN, c = i % CIN;
+            al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
         }
         __syncthreads();
         for (int y = 0; y < W; ++y) {
@@ -337,20 +338,14 @@ __global__ __launch_bounds__(WT) void cnn_wgrad_kernel(WgradArgs a) {
                     // of the product is db[o] = sum_p dZ[p][o]
 #pragma unroll
                     for (int e = 0; e < 8; ++e) B[e] = (bf16)1.f;
-                } else if constexpr (CIN == 32) {
-                    // one tap per 16-column tile: dy, dx uniform across the wave
-                    const int tap = (nt * 16) / 32, c = j % 32, dy = tap / 3 - 1, dx = tap % 3 - 1;
-                    B = shifted8(&al[(c * AH + y + 1 + dy) * AW + 8 * g], dx + 1);
+                } else if (j < NJ) {
+                    const int tap = j / CIN, c = j % CIN, dy = tap / 3 - 1, dx = tap % 3 - 1;
+                    const bf16 *rp = &al[(c * AH + y + 1 + dy) * AW + 1 + dx + 8 * g];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) B[e] = rp[e];
                 } else {
-                    if (j < NJ) {
-                        const int tap = j / CIN, c = j % CIN, dy = tap / 3 - 1, dx = tap % 3 - 1;
-                        const bf16 *rp = &al[(c * AH + y + 1 + dy) * AW + 1 + dx + 8 * g];
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) B[e] = rp[e];
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) B[e] = (bf16)0.f;
-                    }
+                    for (int e = 0; e < 8; ++e) B[e] = (bf16)0.f;
                 }
                 acc[0][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B, acc[0][jj], 0, 0, 0);
                 acc[1][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B, acc[1][jj], 0, 0, 0);
@@ -381,6 +376,153 @@ __global__ __launch_bounds__(WT) void cnn_wgrad_kernel(WgradArgs a) {
     }
 }
 
+// Weight gradients of a 32-channel layer, streamed in bands of R = 16 image
+// rows so that a workgroup needs 78 KB of LDS and two fit a CU: while one
+// stages a band from HBM the other runs its MFMAs.  Eight waves per
+// workgroup; wave w < 6 owns the input row offset dy = w / 2 - 1 and the
+// channel half w % 2 for all three horizontal taps and both halves of the
+// output channels (6 accumulators): the two 16-byte reads of an input row
+// segment give all three dx shifts in registers, so a band row costs a wave
+// 4 LDS reads for 6 MFMAs.  Wave 6 takes the bias tile (B all ones), wave 7
+// only stages.  Per stamp: bands y0 = 0 and 16 (15 rows, row 31 is zero).
+struct Wg32 {
+    static constexpr int R = 16, W = 31, NJ = 288;
+    // channel strides padded to an odd number of 16-byte slots: the 16
+    // channels a wave reads at once fall in distinct LDS banks
+    static constexpr int DZS = R * 32 + 8;      // dZ [32 o][R rows][32 x], x = 31 is zero
+    static constexpr int AR = R + 2, AW = 40;   // input rows y0 - 1 .. y0 + R, column x + 1
+    static constexpr int AS = AR * AW + 8;
+    static constexpr int NDZ = R * 16, NITEM = NDZ + AR * 16;   // pixel pairs per band
+    static constexpr size_t bytes() { return ((size_t)32 * DZS + (size_t)32 * AS) * 2; }
+};
+constexpr int WT32 = 512;
+
+__global__ __launch_bounds__(WT32, 4) void cnn_wgrad32_kernel(WgradArgs a) {
+    using S = Wg32;
+    constexpr int R = S::R, W = S::W, NJ = S::NJ, DZS = S::DZS, AW = S::AW, AS = S::AS;
+    extern __shared__ __align__(16) bf16 sm[];
+    bf16 *dzl = sm;
+    bf16 *al = sm + 32 * DZS;
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, g = lane >> 4;
+    floatx4 acc[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // columns 32..39 of the input rows are read by the dx = +1 shifts of the
+    // last segment and are never staged: zero them once
+    for (int i = tid; i < (int)(S::bytes() / 16); i += WT32) ((uint4 *)sm)[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    const int dy = wave / 2 - 1, c = (wave & 1) * 16 + col;
+    // a band item is a pair of horizontally adjacent pixels, all 32
+    // channels (eight 16-byte loads); item q < NDZ is dZ row y0 + q / 16,
+    // x = (2m, 2m+1), the rest input row y0 - 1 + r, x = (2m-1, 2m); pixels
+    // outside the stamp read as zero
+    auto load = [&](const bf16 *dzs, const bf16 *as, int y0, int q, uint4 (&v)[2][4]) {
+        const bool isdz = q < S::NDZ;
+        const int qq = isdz ? q : q - S::NDZ, m = qq % 16;
+        const int y = isdz ? y0 + qq / 16 : y0 - 1 + qq / 16;
+        const int x0 = isdz ? 2 * m : 2 * m - 1;
+        const bf16 *base = isdz ? dzs : as;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int x = x0 + p;
+            const bool in = y >= 0 && y < W && x >= 0 && x < W;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                v[p][k] = in ? ((const uint4 *)(base + (size_t)(y * W + x) * 32))[k] : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    auto store = [&](int q, const uint4 (&v)[2][4]) {
+        const bool isdz = q < S::NDZ;
+        const int qq = isdz ? q : q - S::NDZ, m = qq % 16, r = qq / 16;
+        uint32_t *dst = isdz ? (uint32_t *)&dzl[r * 32 + 2 * m] : (uint32_t *)&al[r * AW + 2 * m];
+        const int cs = (isdz ? DZS : AS) / 2;   // channel stride in words
+#pragma unroll
+        for (int o = 0; o < 32; ++o) {
+            const uint32_t wa = (&v[0][o >> 3].x)[(o >> 1) & 3], wb = (&v[1][o >> 3].x)[(o >> 1) & 3];
+            dst[o * cs] = (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
+        }
+    };
+    const int q1 = tid + WT32;
+    const bool two = q1 < S::NITEM;
+    const int nv = *a.nvalid;
+    for (int k = b; k < nv; k += gridDim.x) {
+        const int n = a.order[k];
+        const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
+        const bf16 *as = a.ain + (size_t)n * a.npx * 32;
+        for (int y0 = 0; y0 < W; y0 += R) {
+            {
+                uint4 v0[2][4];
+                load(dzs, as, y0, tid, v0);
+                store(tid, v0);
+            }
+            if (two) {
+                uint4 v1[2][4];
+                load(dzs, as, y0, q1, v1);
+                store(q1, v1);
+            }
+            __syncthreads();
+            const int nr = min(R, W - y0);
+            if (wave < 6) {
+#pragma unroll 2
+                for (int i = 0; i < nr; ++i) {
+                    const bf16x8 A0 = *(const bf16x8 *)&dzl[col * DZS + i * 32 + 8 * g];
+                    const bf16x8 A1 = *(const bf16x8 *)&dzl[(16 + col) * DZS + i * 32 + 8 * g];
+                    const bf16 *rp = &al[c * AS + (i + 1 + dy) * AW + 8 * g];
+                    const uint4 lo = *(const uint4 *)rp, hi = *(const uint4 *)(rp + 8);
+                    uint4 s1, s2;
+                    s1.x = __builtin_amdgcn_alignbyte(lo.y, lo.x, 2);
+                    s1.y = __builtin_amdgcn_alignbyte(lo.z, lo.y, 2);
+                    s1.z = __builtin_amdgcn_alignbyte(lo.w, lo.z, 2);
+                    s1.w = __builtin_amdgcn_alignbyte(hi.x, lo.w, 2);
+                    s2 = make_uint4(lo.y, lo.z, lo.w, hi.x);
+                    const bf16x8 B0 = *(const bf16x8 *)&lo, B1 = *(const bf16x8 *)&s1,
+                                 B2 = *(const bf16x8 *)&s2;
+                    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B0, acc[0][0], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B0, acc[1][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B1, acc[0][1], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1, acc[1][1], 0, 0, 0);
+                    acc[0][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B2, acc[0][2], 0, 0, 0);
+                    acc[1][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B2, acc[1][2], 0, 0, 0);
+                }
+            } else if (wave == 6) {
+                // the bias tile: every column of B is one, so each column of
+                // the product is db[o] = sum_p dZ[p][o]
+                bf16x8 ones;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) ones[e] = (bf16)1.f;
+                for (int i = 0; i < nr; ++i) {
+                    const bf16x8 A0 = *(const bf16x8 *)&dzl[col * DZS + i * 32 + 8 * g];
+                    const bf16x8 A1 = *(const bf16x8 *)&dzl[(16 + col) * DZS + i * 32 + 8 * g];
+                    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, ones, acc[0][0], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, ones, acc[1][0], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // partials: dW[o][tap][c] at o * NJ + tap * 32 + c, tap = (dy + 1) * 3 + (dx + 1); db after
+    float *part = a.part + (size_t)b * (32 * NJ + 32);
+    if (wave < 6) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int j = ((dy + 1) * 3 + dx) * 32 + c;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part[(mt * 16 + 4 * g + r) * NJ + j] = acc[mt][dx][r];
+        }
+    } else if (wave == 6 && col == 0) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[32 * NJ + mt * 16 + 4 * g + r] = acc[mt][0][r];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pooling (one workgroup per stamp) and head (one per tile).
 struct HeadArgs {
@@ -395,52 +537,35 @@ struct HeadArgs {
     int S, npx, nout, T;
 };
 
-// Spatial mean of the last activation, one workgroup per stamp: a thread
-// sums 8 channels (one 16-byte load) of every 64th pixel; 64 threads share a
-// channel group and are summed through LDS.  Invalid stamps get zeros.
-__global__ __launch_bounds__(NT) void cnn_pool_kernel(HeadArgs a) {
-    __shared__ float red[NT][9];
-    const int n = blockIdx.x, tid = threadIdx.x;
-    if (!a.valid[n]) {
-        if (tid < 32) a.pool[(size_t)n * 32 + tid] = 0.f;
-        return;
+// Per tile: mean of the pooled features over its valid stamps (the band
+// sums of the last forward convolution / pixels), linear head.  Thread
+// group k of 8 takes stamps k, k + 8, ...; the groups are added in order.
+constexpr int HF_T = 256;
+__global__ __launch_bounds__(HF_T) void cnn_head_fwd_kernel(HeadArgs a) {
+    __shared__ float qp[HF_T / 32][32];
+    __shared__ int np[HF_T / 32];
+    __shared__ float qs[32];
+    const int t = blockIdx.x, tid = threadIdx.x, c = tid & 31, grp = tid >> 5;
+    float qsum = 0.f;
+    int nv = 0;
+    for (int s = grp; s < a.S; s += HF_T / 32) {
+        const int n = t * a.S + s;
+        if (!a.valid[n]) continue;
+        ++nv;
+        qsum += a.pool[(size_t)n * 64 + c] + a.pool[(size_t)n * 64 + 32 + c];
     }
-    const uint4 *src = (const uint4 *)(a.a4 + (size_t)n * a.npx * 32);
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int i = tid; i < a.npx * 4; i += NT) {
-        const uint4 v = src[i];
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            acc[2 * e] += __uint_as_float(w[e] << 16);
-            acc[2 * e + 1] += __uint_as_float(w[e] & 0xffff0000u);
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) red[tid][e] = acc[e];
+    qp[grp][c] = qsum;
+    if (c == 0) np[grp] = nv;
     __syncthreads();
     if (tid < 32) {
-        const int g = tid >> 3, e = tid & 7;          // channel tid = 8 g + e
         float sum = 0.f;
-        for (int j = g; j < NT; j += 4) sum += red[j][e];
-        a.pool[(size_t)n * 32 + tid] = sum / (float)a.npx;
-    }
-}
-
-// Per tile: mean of the pooled features over its valid stamps, linear head.
-__global__ void cnn_head_fwd_kernel(HeadArgs a) {
-    __shared__ float qs[32];
-    const int t = blockIdx.x, tid = threadIdx.x;
-    if (tid < 32) {
-        float qsum = 0.f;
-        int nv = 0;
-        for (int s = 0; s < a.S; ++s) {
-            const int n = t * a.S + s;
-            if (!a.valid[n]) continue;
-            ++nv;
-            qsum += a.pool[(size_t)n * 32 + tid];
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < HF_T / 32; ++k) {
+            sum += qp[k][tid];
+            n += np[k];
         }
-        qs[tid] = nv > 0 ? qsum / (float)nv : 0.f;
+        qs[tid] = n > 0 ? sum / ((float)n * (float)a.npx) : 0.f;
         a.q[t * 32 + tid] = qs[tid];
     }
     __syncthreads();
@@ -478,9 +603,12 @@ __global__ void cnn_head_bwd_kernel(HeadArgs a) {
     float *part = a.part + (size_t)t * (a.nout * 32 + a.nout);
     for (int i = tid; i < a.nout * 32; i += 64) part[i] = dout[i / 32] * a.q[t * 32 + i % 32];
     if (tid < a.nout) part[a.nout * 32 + tid] = dout[tid];
+    int nv = 0;                                 // valid stamps of the tile (one wave)
+    for (int s0 = 0; s0 < a.S; s0 += 64) {
+        const bool v = s0 + tid < a.S && a.valid[t * a.S + s0 + tid] != 0;
+        nv += __popcll(__ballot(v));
+    }
     if (tid < 32) {
-        int nv = 0;
-        for (int s = 0; s < a.S; ++s) nv += a.valid[t * a.S + s] != 0;
         const float inv = nv > 0 ? 1.0f / ((float)nv * (float)a.npx) : 0.f;
         float s = 0.f;
         for (int j = 0; j < a.nout; ++j) s += a.hw[j * 32 + tid] * dout[j];
@@ -598,7 +726,18 @@ __global__ void cnn_adam_kernel(float *w, const float *g, float *m, float *v, si
 
 // bf16 copies of layer l: forward [o][kp] (zero padded) and, for the
 // backward data pass, transposed-flipped [c][tap'*32 + o] = W[o][8 - tap'][c]
-__global__ void cnn_pack_kernel(const float *w, int cin, int kp, bf16 *wb, bf16 *wt) {
+struct PackArgs {
+    const float *w[4];
+    bf16 *wb[4], *wt[4];                        // wt[0] is null (no data gradient below layer 0)
+    int cin[4], kp[4];
+};
+
+// every layer in one launch: blockIdx.y is the layer
+__global__ void cnn_pack_kernel(PackArgs pa) {
+    const int l = blockIdx.y;
+    const float *w = pa.w[l];
+    const int cin = pa.cin[l], kp = pa.kp[l];
+    bf16 *wb = pa.wb[l], *wt = pa.wt[l];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 32 * kp) {
         const int o = i / kp, k = i % kp;
@@ -922,28 +1061,41 @@ int conv_launch(argus_ctx *ctx, const ConvArgs &ca) {
     size_t lds = (size_t)ConvShape<CIN>::ACT * sizeof(bf16);
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_conv_kernel<CIN, MODE>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n), dim3(conv_threads<MODE>()), lds,
+    hipLaunchKernelGGL((cnn_conv_kernel<CIN, MODE>), dim3(ca.n * ConvShape<CIN>::NBAND),
+                       dim3(conv_threads<MODE>()), lds,
                        ctx->stream, ca);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
 
-template <int CIN>
-int wgrad_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
-    size_t lds = WgradShape<CIN>::bytes();
-    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad_kernel<CIN>,
+int wgrad2_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
+    size_t lds = Wg2::bytes();
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad2_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((cnn_wgrad_kernel<CIN>), dim3(T * wa.G), dim3(WT), lds, ctx->stream, wa);
+    hipLaunchKernelGGL(cnn_wgrad2_kernel, dim3(T * WG_GROUPS), dim3(WT), lds, ctx->stream, wa);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
+    return ARGUS_OK;
+}
+
+int wgrad32_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
+    size_t lds = Wg32::bytes();
+    ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad32_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(cnn_wgrad32_kernel, dim3(T * WG_GROUPS), dim3(WT32), lds, ctx->stream, wa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
 
 int cnn_pack(argus_ctx *ctx, argus_cnn *c) {
+    PackArgs pa;
     for (int l = 0; l < 4; ++l) {
-        hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 288 + 255) / 256), dim3(256), 0, ctx->stream,
-                           (const float *)(c->master + c->w_off[l]), c->cin[l], c->kp[l], c->wb[l],
-                           l > 0 ? c->wt[l] : (bf16 *)nullptr);
+        pa.w[l] = c->master + c->w_off[l];
+        pa.wb[l] = c->wb[l];
+        pa.wt[l] = l > 0 ? c->wt[l] : nullptr;
+        pa.cin[l] = c->cin[l];
+        pa.kp[l] = c->kp[l];
     }
+    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 288 + 255) / 256, 4), dim3(256), 0, ctx->stream, pa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
@@ -963,6 +1115,7 @@ int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t 
         ca.w = c->wb[l];
         ca.bias = c->master + c->b_off[l];
         ca.out = c->act[l];
+        ca.pool = l == 3 ? c->pool : nullptr;
         int rc = l == 0 ? conv_launch<2, 0>(ctx, ca) : conv_launch<32, 0>(ctx, ca);
         if (rc) return rc;
     }
@@ -971,8 +1124,7 @@ int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t 
     ha.target = nullptr; ha.q = c->q; ha.out = c->out; ha.dz4 = nullptr; ha.part = nullptr;
     ha.loss_part = nullptr; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
     ha.pool = c->pool; ha.dq = c->dq;
-    hipLaunchKernelGGL(cnn_pool_kernel, dim3(T * c->S), dim3(NT), 0, ctx->stream, ha);
-    hipLaunchKernelGGL(cnn_head_fwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
+    hipLaunchKernelGGL(cnn_head_fwd_kernel, dim3(T), dim3(HF_T), 0, ctx->stream, ha);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
@@ -1095,7 +1247,7 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     bytes += (size_t)max_tiles * (32 + c->nout) * sizeof(float);    // q, out
     bytes += (size_t)max_tiles * WG_GROUPS * part_stride * sizeof(float);
     bytes += (size_t)max_tiles * sizeof(double) + 4096;
-    bytes += (N + max_tiles) * 32 * sizeof(float) + 512;            // pool, dq
+    bytes += (2 * N + max_tiles) * 32 * sizeof(float) + 512;        // pool (two bands), dq
     bytes += N * sizeof(int32_t) + 512;                              // order, nvalid
     if (hipMalloc(&c->mem, bytes) != hipSuccess) {
         delete c;
@@ -1117,7 +1269,7 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     c->out = (float *)take((size_t)max_tiles * c->nout * 4);
     c->part = (float *)take((size_t)max_tiles * WG_GROUPS * part_stride * 4);
     c->loss_part = (double *)take((size_t)max_tiles * 8);
-    c->pool = (float *)take(N * 32 * 4);
+    c->pool = (float *)take(N * 64 * 4);
     c->dq = (float *)take((size_t)max_tiles * 32 * 4);
     c->order = (int32_t *)take(N * 4);
     c->nvalid = (int32_t *)take(64);
@@ -1203,12 +1355,11 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
         WgradArgs wa;
         wa.dz = c->dz[cur];
         wa.ain = l == 0 ? Xb : c->act[l - 1];
-        wa.valid = valid;
+        wa.order = c->order;                         // compacted by this step's forward pass
+        wa.nvalid = c->nvalid;
         wa.part = c->part;
-        wa.S = c->S;
         wa.npx = c->npx;
-        wa.G = WG_GROUPS;
-        rc = l == 0 ? wgrad_launch<2>(ctx, wa, T) : wgrad_launch<32>(ctx, wa, T);
+        rc = l == 0 ? wgrad2_launch(ctx, wa, T) : wgrad32_launch(ctx, wa, T);
         if (rc) return rc;
         const int len = 32 * 9 * c->cin[l] + 32;
         hipLaunchKernelGGL(cnn_reduce_kernel, dim3((len + RED_W - 1) / RED_W), dim3(RED_W * RED_G), 0,
@@ -1221,6 +1372,7 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
             ca.w = c->wt[l];
             ca.gate = c->act[l - 1];
             ca.bias = nullptr;
+            ca.pool = nullptr;
             ca.order = c->order;                     // compacted by this step's forward pass
             ca.nvalid = c->nvalid;
             ca.out = c->dz[cur ^ 1];
