@@ -419,6 +419,29 @@ def surrogate_leg(args, torch, argus):
     ms_eval = timed(evaluation_mode)
     ok = [r for r in rows if r["status"] == 0]
     med = lambda k: float(np.nanmedian([r[k] for r in ok]))
+    # sparse tiles: the same conditions with 300 stars per 1024^2 frame (~19
+    # per tile, against ~190): the gain is the kernel error against the fit
+    # on the noise-free frames, where that fit exists
+    sparse = [sur.Frame(ctx, W, H, 300, 9100 + i, cond, noise_free=True) for i in range(4)]
+    rows_sp = sur.evaluate(ctx, path, sparse, B)
+    del sparse
+    sp_truth = [r for r in rows_sp if r["truth_status"] == 0]
+    sp_ok = [r for r in sp_truth if r["plain_status"] == 0]
+    sp_failed = [r for r in sp_truth if r["plain_status"] != 0]
+    smed = lambda rs, k: (round(float(np.nanmedian([r[k] for r in rs])), 4) if rs else None)
+    sparse_res = {"stars_per_frame": 300, "tiles": len(rows_sp),
+                  "noise_free_fit_ok": len(sp_truth), "plain_fit_failed": len(sp_failed),
+                  "acceptance": (round(float(np.mean([r["accepted"] for r in sp_ok])), 3)
+                                 if sp_ok else None),
+                  "kernel_err_vs_noise_free": {"plain": smed(sp_ok, "err_plain"),
+                                               "surrogate": smed(sp_ok, "err_sur"),
+                                               "surrogate_where_plain_failed":
+                                                   smed(sp_failed, "err_sur")},
+                  "model_err_vs_noise_free": {"plain": smed(sp_ok, "model_err_plain"),
+                                              "surrogate": smed(sp_ok, "model_err_sur")},
+                  "surrogate_better_frac": (round(float(np.mean([r["err_sur"] < r["err_plain"]
+                                                                for r in sp_ok])), 3)
+                                            if sp_ok else None)}
     res = {"train": {"samples": n, "frames": args.sur_frames, "epochs": args.sur_epochs,
                      "generate_s": round(t_gen, 2), "samples_per_s": round(samples_s, 1),
                      "valid_stamps_per_sample": round(stamps_per_sample, 2),
@@ -435,6 +458,7 @@ def surrogate_leg(args, torch, argus):
                                         "surrogate": round(med("err_sur"), 4)},
            "model_err_vs_noise_free": {"plain": round(med("model_err_plain"), 4),
                                        "surrogate": round(med("model_err_sur"), 4)},
+           "sparse": sparse_res,
            "workload": f"train: {args.sur_frames} 1024^2 pairs (seeing 1.5-4.0, ell 0-0.2, sky "
                        f"200-3000), noise-free plain-fit targets, {args.sur_epochs} epochs, batch "
                        f"32 tiles; infer: 4 configuration-1 frames, 4x4 tiles, 15x15 kernel"}

@@ -32,7 +32,8 @@ struct argus_cnn {
     bf16 *act[4] = {}, *dz[2] = {};            // activations, two dZ ping-pong buffers
     float *q = nullptr, *out = nullptr;         // per tile pooled features and outputs
     float *pool = nullptr, *dq = nullptr;       // per stamp pooled features, per tile dq
-    float *part = nullptr;                      // per tile gradient partials
+    float *part = nullptr;                      // gradient partials of layers 0..3 and the head
+    size_t part_off[5] = {};                    // each block's region (floats from part)
     double *loss_part = nullptr;
     int32_t *order = nullptr, *nvalid = nullptr;   // the valid stamps' indices, their count
     int step = 0;
@@ -616,12 +617,16 @@ __global__ void cnn_head_bwd_kernel(HeadArgs a) {
     }
 }
 
-// dZ of the last layer, one workgroup per valid stamp: the pooled-feature
-// gradient gated by the ReLU of the forward activation, 8 channels per
-// 16-byte load and store.
-__global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a) {
-    const int n = blockIdx.x, tid = threadIdx.x;
-    if (!a.valid[n]) return;
+// dZ of the last layer, DZ4_SPLIT workgroups per valid stamp (compacted
+// order; the rest of the grid leaves at once): the pooled-feature gradient
+// gated by the ReLU of the forward activation, 8 channels per 16-byte load
+// and store.
+constexpr int DZ4_SPLIT = 4;
+__global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a, const int32_t *order,
+                                                     const int32_t *nvalid) {
+    const int k = blockIdx.x / DZ4_SPLIT, part = blockIdx.x % DZ4_SPLIT, tid = threadIdx.x;
+    if (k >= *nvalid) return;
+    const int n = order[k];
     const int t = n / a.S;
     const int g = tid & 3;                       // channels 8g .. 8g+7 (NT is a multiple of 4)
     float dq[8];
@@ -629,7 +634,10 @@ __global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a) {
     for (int e = 0; e < 8; ++e) dq[e] = a.dq[t * 32 + 8 * g + e];
     const uint4 *src = (const uint4 *)(a.a4 + (size_t)n * a.npx * 32);
     uint4 *dst = (uint4 *)(a.dz4 + (size_t)n * a.npx * 32);
-    for (int i = tid; i < a.npx * 4; i += NT) {
+    // whole pixels per part (four 16-byte pieces each), so piece i holds
+    // channels 8 (i % 4) .. +7 = 8 g
+    const int i0 = (part * a.npx / DZ4_SPLIT) * 4, i1 = ((part + 1) * a.npx / DZ4_SPLIT) * 4;
+    for (int i = i0 + tid; i < i1; i += NT) {
         const uint4 v = src[i];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
         uint32_t o[4];
@@ -676,9 +684,20 @@ __global__ __launch_bounds__(CMP_T) void cnn_compact_kernel(const uint8_t *valid
 // consecutive ranges of the partials (each in order, several loads in
 // flight), then the 8 range sums are added in order.
 constexpr int RED_W = 32, RED_G = 8;
-__global__ __launch_bounds__(RED_W * RED_G) void cnn_reduce_kernel(const float *part, int stride,
-                                                                   int len, int T, float *dst) {
+struct ReduceArgs {
+    const float *part[5];                       // per gradient block: [T][len] partials
+    float *dst[5];
+    int len[5], T[5];
+};
+
+// every gradient block of a step in one launch: blockIdx.y is the block
+__global__ __launch_bounds__(RED_W * RED_G) void cnn_reduce_kernel(ReduceArgs ra) {
     __shared__ float rs[RED_G][RED_W];
+    const int y = blockIdx.y;
+    const float *part = ra.part[y];
+    float *dst = ra.dst[y];
+    const int len = ra.len[y], stride = len, T = ra.T[y];
+    if ((int)blockIdx.x * RED_W >= len) return;     // uniform: this block is past the gradient
     const int j = threadIdx.x % RED_W, g = threadIdx.x / RED_W;
     const int i = blockIdx.x * RED_W + j;
     const int t0 = (int)((int64_t)g * T / RED_G), t1 = (int)((int64_t)(g + 1) * T / RED_G);
@@ -1240,15 +1259,21 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     c->P = off;
     const size_t N = (size_t)max_tiles * c->S, A = N * c->npx * 32;
     const size_t head_stride = (size_t)c->nout * 32 + c->nout;
-    const size_t part_stride = 32 * 9 * 32 + 32 > head_stride ? 32 * 9 * 32 + 32 : head_stride;
     size_t bytes = 4 * c->P * sizeof(float);                        // master, grad, m, v
     bytes += 4 * 32 * 288 * sizeof(bf16) * 2;                       // wb, wt
     bytes += (4 * A + 2 * A) * sizeof(bf16);                        // act, dz
     bytes += (size_t)max_tiles * (32 + c->nout) * sizeof(float);    // q, out
-    bytes += (size_t)max_tiles * WG_GROUPS * part_stride * sizeof(float);
+    size_t part_len = 0;                        // per workgroup (layers) or tile (head) partials
+    for (int l = 0; l < 5; ++l) {
+        c->part_off[l] = part_len;
+        part_len += l < 4 ? (size_t)max_tiles * WG_GROUPS * (32 * 9 * c->cin[l] + 32)
+                          : (size_t)max_tiles * head_stride;
+    }
+    bytes += part_len * sizeof(float);
     bytes += (size_t)max_tiles * sizeof(double) + 4096;
     bytes += (2 * N + max_tiles) * 32 * sizeof(float) + 512;        // pool (two bands), dq
     bytes += N * sizeof(int32_t) + 512;                              // order, nvalid
+    bytes += 32 * 256;                                               // 256-byte alignment of each region
     if (hipMalloc(&c->mem, bytes) != hipSuccess) {
         delete c;
         return argus_fail(ctx, ARGUS_ENOMEM, "cnn buffers (%zu bytes)", bytes);
@@ -1267,7 +1292,7 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     for (int l = 0; l < 2; ++l) c->dz[l] = (bf16 *)take(A * 2);
     c->q = (float *)take((size_t)max_tiles * 32 * 4);
     c->out = (float *)take((size_t)max_tiles * c->nout * 4);
-    c->part = (float *)take((size_t)max_tiles * WG_GROUPS * part_stride * 4);
+    c->part = (float *)take(part_len * 4);
     c->loss_part = (double *)take((size_t)max_tiles * 8);
     c->pool = (float *)take(N * 64 * 4);
     c->dq = (float *)take((size_t)max_tiles * 32 * 4);
@@ -1338,14 +1363,19 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     // head backward -> dZ of layer 3 (in dz[1])
     HeadArgs ha;
     ha.a4 = c->act[3]; ha.valid = valid; ha.hw = c->master + c->hw_off; ha.hb = c->master + c->hb_off;
-    ha.target = target; ha.q = c->q; ha.out = c->out; ha.dz4 = c->dz[1]; ha.part = c->part;
+    ha.target = target; ha.q = c->q; ha.out = c->out; ha.dz4 = c->dz[1];
+    ha.part = c->part + c->part_off[4];
     ha.loss_part = c->loss_part; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
     ha.pool = c->pool; ha.dq = c->dq;
     hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
-    hipLaunchKernelGGL(cnn_dz4_kernel, dim3(T * c->S), dim3(NT), 0, ctx->stream, ha);
-    const int hlen = c->nout * 32 + c->nout;
-    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((hlen + RED_W - 1) / RED_W), dim3(RED_W * RED_G), 0,
-                       ctx->stream, (const float *)c->part, hlen, hlen, T, c->grad + c->hw_off);
+    hipLaunchKernelGGL(cnn_dz4_kernel, dim3(T * c->S * DZ4_SPLIT), dim3(NT), 0, ctx->stream, ha,
+                       (const int32_t *)c->order, (const int32_t *)c->nvalid);
+    // every gradient block is summed by one launch after the last weight gradients
+    ReduceArgs ra;
+    ra.part[4] = ha.part;
+    ra.dst[4] = c->grad + c->hw_off;
+    ra.len[4] = c->nout * 32 + c->nout;
+    ra.T[4] = T;
     hipLaunchKernelGGL(cnn_loss_kernel, dim3(1), dim3(64), 0, ctx->stream,
                        (const double *)c->loss_part, T, loss);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
@@ -1357,15 +1387,14 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
         wa.ain = l == 0 ? Xb : c->act[l - 1];
         wa.order = c->order;                         // compacted by this step's forward pass
         wa.nvalid = c->nvalid;
-        wa.part = c->part;
+        wa.part = c->part + c->part_off[l];
         wa.npx = c->npx;
         rc = l == 0 ? wgrad2_launch(ctx, wa, T) : wgrad32_launch(ctx, wa, T);
         if (rc) return rc;
-        const int len = 32 * 9 * c->cin[l] + 32;
-        hipLaunchKernelGGL(cnn_reduce_kernel, dim3((len + RED_W - 1) / RED_W), dim3(RED_W * RED_G), 0,
-                           ctx->stream, (const float *)c->part, len, len, T * WG_GROUPS,
-                           c->grad + c->w_off[l]);
-        ARGUS_HIP_CHECK(ctx, hipGetLastError());
+        ra.part[l] = wa.part;
+        ra.dst[l] = c->grad + c->w_off[l];
+        ra.len[l] = 32 * 9 * c->cin[l] + 32;
+        ra.T[l] = T * WG_GROUPS;
         if (l > 0) {
             ConvArgs ca;
             ca.in = c->dz[cur];
@@ -1382,6 +1411,11 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
             cur ^= 1;
         }
     }
+    int rx = 0;
+    for (int k = 0; k < 5; ++k) rx = ra.len[k] > rx ? ra.len[k] : rx;
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((rx + RED_W - 1) / RED_W, 5), dim3(RED_W * RED_G), 0,
+                       ctx->stream, ra);
+    ARGUS_HIP_CHECK(ctx, hipGetLastError());
     // Adam on the FP32 master weights, then the bf16 copies
     c->step += 1;
     const float c1 = 1.0f - powf(0.9f, (float)c->step), c2 = 1.0f - powf(0.999f, (float)c->step);

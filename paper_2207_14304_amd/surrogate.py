@@ -325,5 +325,6 @@ def evaluate(ctx, path: "SurrogatePath", frames, B):
                              model_err_plain=float(m_p[t]), model_err_sur=float(m_s[t]),
                              accepted=int(acc[t]), chi2dof_plain=float(rp[t]),
                              chi2dof_final=float(rf[t]),
-                             status=int(st[t]) if st[t] != 0 else int(stt[t])))
+                             status=int(st[t]) if st[t] != 0 else int(stt[t]),
+                             plain_status=int(st[t]), truth_status=int(stt[t])))
     return rows
