@@ -617,16 +617,11 @@ __global__ void cnn_head_bwd_kernel(HeadArgs a) {
     }
 }
 
-// dZ of the last layer, DZ4_SPLIT workgroups per valid stamp (compacted
-// order; the rest of the grid leaves at once): the pooled-feature gradient
-// gated by the ReLU of the forward activation, 8 channels per 16-byte load
-// and store.
+// dZ of the last layer, DZ4_SPLIT items per valid stamp (compacted order),
+// walked by a grid sized to the chip: the pooled-feature gradient gated by
+// the ReLU of the forward activation, 8 channels per 16-byte load and store.
 constexpr int DZ4_SPLIT = 4;
-__global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a, const int32_t *order,
-                                                     const int32_t *nvalid) {
-    const int k = blockIdx.x / DZ4_SPLIT, part = blockIdx.x % DZ4_SPLIT, tid = threadIdx.x;
-    if (k >= *nvalid) return;
-    const int n = order[k];
+__device__ __forceinline__ void dz4_item(const HeadArgs &a, int n, int part, int tid) {
     const int t = n / a.S;
     const int g = tid & 3;                       // channels 8g .. 8g+7 (NT is a multiple of 4)
     float dq[8];
@@ -651,6 +646,13 @@ __global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a, const int32_t *
         }
         dst[i] = uint4{o[0], o[1], o[2], o[3]};
     }
+}
+
+__global__ __launch_bounds__(NT) void cnn_dz4_kernel(HeadArgs a, const int32_t *order,
+                                                     const int32_t *nvalid) {
+    const int nitems = *nvalid * DZ4_SPLIT, tid = threadIdx.x;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+        dz4_item(a, order[item / DZ4_SPLIT], item % DZ4_SPLIT, tid);
 }
 
 // Indices of the valid stamps in increasing order and their count (one
@@ -1368,7 +1370,8 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     ha.loss_part = c->loss_part; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
     ha.pool = c->pool; ha.dq = c->dq;
     hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
-    hipLaunchKernelGGL(cnn_dz4_kernel, dim3(T * c->S * DZ4_SPLIT), dim3(NT), 0, ctx->stream, ha,
+    const int dz4_grid = std::max(1, std::min(T * c->S * DZ4_SPLIT, 8 * std::max(ctx->n_cu, 1)));
+    hipLaunchKernelGGL(cnn_dz4_kernel, dim3(dz4_grid), dim3(NT), 0, ctx->stream, ha,
                        (const int32_t *)c->order, (const int32_t *)c->nvalid);
     // every gradient block is summed by one launch after the last weight gradients
     ReduceArgs ra;
