@@ -175,6 +175,33 @@ def test_cnn_forward_and_gradients_match_oracle(ctx):
     cnn.close()
 
 
+def test_cnn_gradients_dense_tiles_match_oracle(ctx):
+    """Dense tiles (70 valid stamps over 2 tiles, against 32 weight-gradient
+    workgroups): each workgroup accumulates two or three stamps of the
+    compacted list, and the convolutions run both row bands of every stamp."""
+    import torch
+    T = 2
+    counts = [40, 30]
+    xg, xo, valid = _stamp_batch(T, counts, 24)
+    flat = _params(13)
+    p = _from_flat(flat.astype(np.float64))
+    tgt = (0.05 * np.random.default_rng(14).standard_normal((T, 31))).astype(np.float32)
+    cnn = argus.CNN(ctx, max_tiles=T)
+    cnn.set_weights(flat)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cnn.train_step(xg, dev(valid), dev(tgt), 0.0, loss)
+    k = max(counts)
+    oo, cache = sg.forward(p, xo[:, :k], valid[:, :k].astype(np.float64))
+    g_gpu = _from_flat(cnn.get_grads().astype(np.float64))
+    g_or = sg.backward(p, cache, oo, tgt.astype(np.float64))
+    assert abs(float(host(loss)[0]) / sg.loss(oo, tgt) - 1) <= 2e-2
+    for key in g_or:
+        e = _rel(g_gpu[key], g_or[key])
+        print("grad", key, e)
+        assert e <= 2e-2, key
+    cnn.close()
+
+
 def test_adam_first_step(ctx):
     import torch
     T = 2
