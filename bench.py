@@ -34,8 +34,8 @@ PEAK_FP32_PUBLISHED = 157.3        # published FP32 vector peak (packed FP32 ops
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--width", type=int, default=9576)
     p.add_argument("--height", type=int, default=6388)
     p.add_argument("--stars", type=int, default=60000)
