@@ -36,6 +36,7 @@ struct argus_cnn {
     size_t part_off[5] = {};                    // each block's region (floats from part)
     double *loss_part = nullptr;
     int32_t *order = nullptr, *nvalid = nullptr;   // the valid stamps' indices, their count
+    int32_t *ticket = nullptr;                  // head workgroups done in a training step
     int step = 0;
     void *mem = nullptr;
 };
@@ -535,17 +536,25 @@ struct HeadArgs {
     float *part;                                // head gradient partials [tiles][nout*32 + nout]
     double *loss_part;
     float *pool, *dq;                           // per stamp pooled features, per tile dq
+    double *loss;                               // training: the batch loss
+    int32_t *ticket;                            // training: workgroups done (zero between calls)
     int S, npx, nout, T;
 };
 
 // Per tile: mean of the pooled features over its valid stamps (the band
 // sums of the last forward convolution / pixels), linear head.  Thread
 // group k of 8 takes stamps k, k + 8, ...; the groups are added in order.
+// TRAIN adds the head's backward pass in the same workgroup: the tile's
+// loss, its head gradient partials and the gradient of the pooled features
+// (already divided by valid stamps x pixels for the spread below); the last
+// workgroup to finish sums the tiles' losses in tile order.
 constexpr int HF_T = 256;
-__global__ __launch_bounds__(HF_T) void cnn_head_fwd_kernel(HeadArgs a) {
+template <bool TRAIN>
+__global__ __launch_bounds__(HF_T) void cnn_head_kernel(HeadArgs a) {
     __shared__ float qp[HF_T / 32][32];
     __shared__ int np[HF_T / 32];
     __shared__ float qs[32];
+    __shared__ int s_nv;
     const int t = blockIdx.x, tid = threadIdx.x, c = tid & 31, grp = tid >> 5;
     float qsum = 0.f;
     int nv = 0;
@@ -568,52 +577,57 @@ __global__ __launch_bounds__(HF_T) void cnn_head_fwd_kernel(HeadArgs a) {
         }
         qs[tid] = n > 0 ? sum / ((float)n * (float)a.npx) : 0.f;
         a.q[t * 32 + tid] = qs[tid];
+        if (tid == 0) s_nv = n;
     }
     __syncthreads();
+    float o = 0.f;
     if (tid < a.nout) {
-        float o = a.hb[tid];
+        o = a.hb[tid];
         for (int k = 0; k < 32; ++k) o += a.hw[tid * 32 + k] * qs[k];
         a.out[t * a.nout + tid] = o;
     }
-}
-
-// Per tile: loss, head gradient partials and the gradient of the pooled
-// features, already divided by (valid stamps x pixels) for the spread below.
-__global__ void cnn_head_bwd_kernel(HeadArgs a) {
-    __shared__ float dout[64];
-    __shared__ double lred[64];
-    const int t = blockIdx.x, tid = threadIdx.x;
-    const float scale = 2.0f / (float)(a.T * a.nout);
-    {
-        double l = 0.0;
-        float d = 0.f;
-        if (tid < a.nout) {
-            const float e = a.out[t * a.nout + tid] - a.target[t * a.nout + tid];
-            d = scale * e;
-            l = (double)e * (double)e / (double)(a.T * a.nout);
+    if constexpr (TRAIN) {
+        __shared__ float dout[64];
+        __shared__ double lred[64];
+        __shared__ int last;
+        const float scale = 2.0f / (float)(a.T * a.nout);
+        if (tid < 64) {
+            double l = 0.0;
+            float d = 0.f;
+            if (tid < a.nout) {
+                const float e = o - a.target[t * a.nout + tid];
+                d = scale * e;
+                l = (double)e * (double)e / (double)(a.T * a.nout);
+            }
+            dout[tid] = d;
+            lred[tid] = l;
         }
-        dout[tid] = d;
-        lred[tid] = l;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double l = 0.0;
-        for (int i = 0; i < 64; ++i) l += lred[i];
-        a.loss_part[t] = l;
-    }
-    float *part = a.part + (size_t)t * (a.nout * 32 + a.nout);
-    for (int i = tid; i < a.nout * 32; i += 64) part[i] = dout[i / 32] * a.q[t * 32 + i % 32];
-    if (tid < a.nout) part[a.nout * 32 + tid] = dout[tid];
-    int nv = 0;                                 // valid stamps of the tile (one wave)
-    for (int s0 = 0; s0 < a.S; s0 += 64) {
-        const bool v = s0 + tid < a.S && a.valid[t * a.S + s0 + tid] != 0;
-        nv += __popcll(__ballot(v));
-    }
-    if (tid < 32) {
-        const float inv = nv > 0 ? 1.0f / ((float)nv * (float)a.npx) : 0.f;
-        float s = 0.f;
-        for (int j = 0; j < a.nout; ++j) s += a.hw[j * 32 + tid] * dout[j];
-        a.dq[t * 32 + tid] = s * inv;
+        __syncthreads();
+        float *part = a.part + (size_t)t * (a.nout * 32 + a.nout);
+        for (int i = tid; i < a.nout * 32; i += HF_T) part[i] = dout[i / 32] * qs[i % 32];
+        if (tid < a.nout) part[a.nout * 32 + tid] = dout[tid];
+        if (tid < 32) {
+            const int n = s_nv;
+            const float inv = n > 0 ? 1.0f / ((float)n * (float)a.npx) : 0.f;
+            float sd = 0.f;
+            for (int j = 0; j < a.nout; ++j) sd += a.hw[j * 32 + tid] * dout[j];
+            a.dq[t * 32 + tid] = sd * inv;
+        }
+        if (tid == 0) {
+            double l = 0.0;
+            for (int i = 0; i < 64; ++i) l += lred[i];
+            a.loss_part[t] = l;
+            __threadfence();                            // the loss part before the ticket
+            last = atomicAdd(a.ticket, 1) == (int)gridDim.x - 1;
+        }
+        __syncthreads();
+        if (last && tid == 0) {
+            __threadfence();                            // every tile's part is visible
+            double sum = 0.0;
+            for (int i = 0; i < a.T; ++i) sum += ((volatile const double *)a.loss_part)[i];
+            *a.loss = sum;
+            *a.ticket = 0;                              // ready for the next step
+        }
     }
 }
 
@@ -725,24 +739,41 @@ __global__ __launch_bounds__(RED_W * RED_G) void cnn_reduce_kernel(ReduceArgs ra
     }
 }
 
-__global__ void cnn_loss_kernel(const double *part, int T, double *loss) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int t = 0; t < T; ++t) s += part[t];
-        *loss = s;
-    }
-}
+// Adam on every FP32 master weight, one thread per weight; a convolution
+// weight's thread also writes its bf16 copies (forward [o][kp] and, above
+// layer 0, transposed-flipped [c][(8 - tap) * 32 + o]), so the copies follow
+// the update without another pass (the zero padding of the forward copy is
+// written once, by cnn_pack).
+struct AdamArgs {
+    float *w, *m, *v;
+    const float *g;
+    size_t n;
+    float lr, c1, c2;
+    size_t w_off[4];
+    int cin[4], kp[4];
+    bf16 *wb[4], *wt[4];
+};
 
-__global__ void cnn_adam_kernel(float *w, const float *g, float *m, float *v, size_t n, float lr,
-                                float c1, float c2) {
+__global__ void cnn_adam_kernel(AdamArgs a) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = 0.9f * m[i] + 0.1f * gi;
-    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    if (i >= a.n) return;
+    const float gi = a.g[i];
+    const float mi = 0.9f * a.m[i] + 0.1f * gi;
+    const float vi = 0.999f * a.v[i] + 0.001f * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float wi = a.w[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + 1e-8f);
+    a.w[i] = wi;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const size_t nl = (size_t)32 * 9 * a.cin[l];
+        if (i >= a.w_off[l] && i < a.w_off[l] + nl) {
+            const int j = (int)(i - a.w_off[l]), cin = a.cin[l];
+            const int o = j / (9 * cin), k = j % (9 * cin), tap = k / cin, c = k % cin;
+            a.wb[l][o * a.kp[l] + k] = (bf16)wi;
+            if (a.wt[l]) a.wt[l][c * 288 + (8 - tap) * 32 + o] = (bf16)wi;
+        }
+    }
 }
 
 // bf16 copies of layer l: forward [o][kp] (zero padded) and, for the
@@ -1122,7 +1153,10 @@ int cnn_pack(argus_ctx *ctx, argus_cnn *c) {
 }
 
 // forward over T tiles of S stamps; activations stay for the backward pass
-int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t *valid, int T) {
+// the head (forward only) is left to the caller when head is false: the
+// training step runs it fused with its backward pass
+int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t *valid, int T,
+                     bool head = true) {
     hipLaunchKernelGGL(cnn_compact_kernel, dim3(1), dim3(CMP_T), 0, ctx->stream, valid, T * c->S,
                        c->order, c->nvalid);
     ConvArgs ca;
@@ -1144,8 +1178,8 @@ int cnn_forward_impl(argus_ctx *ctx, argus_cnn *c, const bf16 *X, const uint8_t 
     ha.a4 = c->act[3]; ha.valid = valid; ha.hw = c->master + c->hw_off; ha.hb = c->master + c->hb_off;
     ha.target = nullptr; ha.q = c->q; ha.out = c->out; ha.dz4 = nullptr; ha.part = nullptr;
     ha.loss_part = nullptr; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
-    ha.pool = c->pool; ha.dq = c->dq;
-    hipLaunchKernelGGL(cnn_head_fwd_kernel, dim3(T), dim3(HF_T), 0, ctx->stream, ha);
+    ha.pool = c->pool; ha.dq = c->dq; ha.loss = nullptr; ha.ticket = nullptr;
+    if (head) hipLaunchKernelGGL(cnn_head_kernel<false>, dim3(T), dim3(HF_T), 0, ctx->stream, ha);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
@@ -1300,7 +1334,9 @@ int argus_cnn_create(argus_ctx *ctx, int max_tiles, argus_cnn **out) {
     c->dq = (float *)take((size_t)max_tiles * 32 * 4);
     c->order = (int32_t *)take(N * 4);
     c->nvalid = (int32_t *)take(64);
-    if (hipMemsetAsync(c->mem, 0, 4 * c->P * sizeof(float) + 1024, ctx->stream) != hipSuccess) {
+    c->ticket = (int32_t *)take(64);
+    if (hipMemsetAsync(c->mem, 0, 4 * c->P * sizeof(float) + 1024, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(c->ticket, 0, 64, ctx->stream) != hipSuccess) {
         (void)hipFree(c->mem);
         delete c;
         return argus_fail(ctx, ARGUS_EHIP, "cnn init");
@@ -1360,16 +1396,16 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     if (T < 1 || T > c->max_tiles) return argus_fail(ctx, ARGUS_ESHAPE, "T %d not in 1..%d", T, c->max_tiles);
     if (!(lr >= 0.f)) return argus_fail(ctx, ARGUS_EINVAL, "learning rate must be >= 0");
     const bf16 *Xb = (const bf16 *)X;
-    int rc = cnn_forward_impl(ctx, c, Xb, valid, T);
+    int rc = cnn_forward_impl(ctx, c, Xb, valid, T, false);
     if (rc) return rc;
-    // head backward -> dZ of layer 3 (in dz[1])
+    // head forward and backward, the loss -> dZ of layer 3 (in dz[1])
     HeadArgs ha;
     ha.a4 = c->act[3]; ha.valid = valid; ha.hw = c->master + c->hw_off; ha.hb = c->master + c->hb_off;
     ha.target = target; ha.q = c->q; ha.out = c->out; ha.dz4 = c->dz[1];
     ha.part = c->part + c->part_off[4];
     ha.loss_part = c->loss_part; ha.S = c->S; ha.npx = c->npx; ha.nout = c->nout; ha.T = T;
-    ha.pool = c->pool; ha.dq = c->dq;
-    hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3(T), dim3(64), 0, ctx->stream, ha);
+    ha.pool = c->pool; ha.dq = c->dq; ha.loss = loss; ha.ticket = c->ticket;
+    hipLaunchKernelGGL(cnn_head_kernel<true>, dim3(T), dim3(HF_T), 0, ctx->stream, ha);
     const int dz4_grid = std::max(1, std::min(T * c->S * DZ4_SPLIT, 8 * std::max(ctx->n_cu, 1)));
     hipLaunchKernelGGL(cnn_dz4_kernel, dim3(dz4_grid), dim3(NT), 0, ctx->stream, ha,
                        (const int32_t *)c->order, (const int32_t *)c->nvalid);
@@ -1379,8 +1415,6 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     ra.dst[4] = c->grad + c->hw_off;
     ra.len[4] = c->nout * 32 + c->nout;
     ra.T[4] = T;
-    hipLaunchKernelGGL(cnn_loss_kernel, dim3(1), dim3(64), 0, ctx->stream,
-                       (const double *)c->loss_part, T, loss);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     // conv layers 3..0: weight gradients, then dZ of the layer below
     int cur = 1;
@@ -1419,13 +1453,23 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
     hipLaunchKernelGGL(cnn_reduce_kernel, dim3((rx + RED_W - 1) / RED_W, 5), dim3(RED_W * RED_G), 0,
                        ctx->stream, ra);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
-    // Adam on the FP32 master weights, then the bf16 copies
+    // Adam on the FP32 master weights and their bf16 copies
     c->step += 1;
     const float c1 = 1.0f - powf(0.9f, (float)c->step), c2 = 1.0f - powf(0.999f, (float)c->step);
+    AdamArgs aa;
+    aa.w = c->master; aa.m = c->m; aa.v = c->v; aa.g = c->grad; aa.n = c->P;
+    aa.lr = lr; aa.c1 = c1; aa.c2 = c2;
+    for (int l = 0; l < 4; ++l) {
+        aa.w_off[l] = c->w_off[l];
+        aa.cin[l] = c->cin[l];
+        aa.kp[l] = c->kp[l];
+        aa.wb[l] = c->wb[l];
+        aa.wt[l] = l > 0 ? c->wt[l] : nullptr;
+    }
     hipLaunchKernelGGL(cnn_adam_kernel, dim3((unsigned)((c->P + 255) / 256)), dim3(256), 0,
-                       ctx->stream, c->master, (const float *)c->grad, c->m, c->v, c->P, lr, c1, c2);
+                       ctx->stream, aa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
-    return cnn_pack(ctx, c);
+    return ARGUS_OK;
 }
 
 int argus_extract_stamps(argus_ctx *ctx, argus_dims d, const float *ref, const float *ref_var,
