@@ -491,7 +491,8 @@ void argus_batch_destroy(argus_batch *batch);
  * [32][9][c_in] (tap = 3 (dy+1) + (dx+1)) then the 32 biases, then the head
  * [31][32] and its 31 biases.  Adam (0.9, 0.999, 1e-8) updates the master.
  * Stamps X are bf16 bit patterns [T][64][31*31][2] (reference, science),
- * valid u8 [T][64].  All device pointers unless marked HOST; calls enqueue on
+ * 4-byte aligned (a pixel's pair is read as one word; ARGUS_EINVAL
+ * otherwise), valid u8 [T][64].  All device pointers unless marked HOST; calls enqueue on
  * the context's stream.  The handle owns its buffers (activations for
  * max_tiles tiles) until argus_cnn_destroy; one handle serves one stream. */
 typedef struct argus_cnn argus_cnn;

@@ -128,10 +128,26 @@ __global__ __launch_bounds__(conv_threads<MODE>(), 4) void cnn_conv_kernel(ConvA
             }
         }
     } else {
-        for (int i = q0 * CIN + tid; i < q1 * CIN; i += CTM) {
-            int p = i / CIN, c = i % CIN;
-            int y = p / W, x = p % W;
-            act[((y - y0 + 1) * PW + (x + 1)) * CIN + c] = src[i];
+        static_assert(CIN == 2, "the input layer has two channels");
+        // one 4-byte word (both channels) per pixel, four loads in flight per
+        // thread before their LDS stores
+        constexpr int U = 4;
+        const uint32_t *src2 = (const uint32_t *)src;
+        for (int i0 = q0 + tid; i0 < q1; i0 += CTM * U) {
+            uint32_t v[U];
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const int i = i0 + e * CTM;
+                v[e] = i < q1 ? src2[i] : 0u;
+            }
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const int i = i0 + e * CTM;
+                if (i < q1) {
+                    const int y = i / W, x = i % W;
+                    *(uint32_t *)&act[((y - y0 + 1) * PW + (x + 1)) * 2] = v[e];
+                }
+            }
         }
     }
     __syncthreads();
@@ -150,15 +166,18 @@ __global__ __launch_bounds__(conv_threads<MODE>(), 4) void cnn_conv_kernel(ConvA
                 for (int e = 0; e < 8; ++e) A[e] = (bf16)0.f;
             }
         } else {
+            // k = ks*32 + 8g + e is tap k / 2, channel k % 2: a lane's 8 values
+            // are both channels of taps ks*16 + 4g .. +3, one 4-byte word each
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = ks * 32 + 8 * g + e, tap = k / CIN, c = k % CIN;
-                bf16 v = (bf16)0.f;
+            for (int e2 = 0; e2 < 4; ++e2) {
+                const int tap = ks * 16 + 4 * g + e2;
+                uint32_t w = 0u;
                 if (pin && tap < 9) {
                     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                    v = act[((y + 1 + dy) * PW + (x + 1 + dx)) * CIN + c];
+                    w = *(const uint32_t *)&act[((y + 1 + dy) * PW + (x + 1 + dx)) * 2];
                 }
-                A[e] = v;
+                A[2 * e2] = __builtin_bit_cast(bf16, (uint16_t)(w & 0xffffu));
+                A[2 * e2 + 1] = __builtin_bit_cast(bf16, (uint16_t)(w >> 16));
             }
         }
         return A;
@@ -321,9 +340,10 @@ __global__ __launch_bounds__(WT) void cnn_wgrad2_kernel(WgradArgs a) {
                     (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
             }
         }
-        for (int i = tid; i < a.npx * CIN; i += WT) {
-            int p = i / CIN, c = i % CIN;
-            al[(c * AH + p / W + 1) * AW + p % W + 1] = as[i];
+        for (int p = tid; p < a.npx; p += WT) {   // both channels of a pixel: one 4-byte load
+            const uint32_t w = ((const uint32_t *)as)[p];
+            al[(0 * AH + p / W + 1) * AW + p % W + 1] = __builtin_bit_cast(bf16, (uint16_t)(w & 0xffffu));
+            al[(1 * AH + p / W + 1) * AW + p % W + 1] = __builtin_bit_cast(bf16, (uint16_t)(w >> 16));
         }
         __syncthreads();
         for (int y = 0; y < W; ++y) {
@@ -1381,6 +1401,7 @@ int argus_cnn_forward(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const uin
                       float *out) {
     if (!ctx || !c || !X || !valid || !out) return ARGUS_EINVAL;
     ctx->err.clear();
+    if ((uintptr_t)X % 4) return argus_fail(ctx, ARGUS_EINVAL, "stamps X must be 4-byte aligned");
     if (T < 1 || T > c->max_tiles) return argus_fail(ctx, ARGUS_ESHAPE, "T %d not in 1..%d", T, c->max_tiles);
     int rc = cnn_forward_impl(ctx, c, (const bf16 *)X, valid, T);
     if (rc) return rc;
@@ -1393,6 +1414,7 @@ int argus_cnn_train_step(argus_ctx *ctx, argus_cnn *c, const uint16_t *X, const 
                          const float *target, int T, float lr, double *loss) {
     if (!ctx || !c || !X || !valid || !target || !loss) return ARGUS_EINVAL;
     ctx->err.clear();
+    if ((uintptr_t)X % 4) return argus_fail(ctx, ARGUS_EINVAL, "stamps X must be 4-byte aligned");
     if (T < 1 || T > c->max_tiles) return argus_fail(ctx, ARGUS_ESHAPE, "T %d not in 1..%d", T, c->max_tiles);
     if (!(lr >= 0.f)) return argus_fail(ctx, ARGUS_EINVAL, "learning rate must be >= 0");
     const bf16 *Xb = (const bf16 *)X;

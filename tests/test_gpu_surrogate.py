@@ -285,6 +285,11 @@ def test_cnn_rejects_bad_shapes(ctx):
     out = empty((3, 31), torch.float32)
     with pytest.raises(argus.ArgusError):
         cnn.forward(x, v, out)
+    # stamps 2 bytes off a 4-byte boundary are refused before any launch
+    xm = torch.zeros(2 * S * NPX * 2 + 1, dtype=torch.bfloat16, device="cuda")[1:].view(2, S, NPX, 2)
+    assert xm.data_ptr() % 4 == 2
+    with pytest.raises(argus.ArgusError):
+        cnn.forward(xm, v[:2], empty((2, 31), torch.float32))
     with pytest.raises(ValueError):
         cnn.set_weights(np.zeros(10, np.float32))
     cnn.close()
