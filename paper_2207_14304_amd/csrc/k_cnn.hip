@@ -44,7 +44,6 @@ struct argus_cnn {
 namespace {
 
 constexpr int NT = 256;
-constexpr int WT = 1024;       // weight-gradient workgroups (one per CU by LDS): 16 waves
 
 __device__ __forceinline__ float bf2f(bf16 x) { return (float)x; }
 
@@ -286,118 +285,6 @@ struct WgradArgs {
     int npx;
 };
 
-// The first layer (2 input channels, 18 weight columns plus the bias) is
-// bound by staging its dZ: one workgroup holds a whole stamp (69 KB, two
-// per CU), and three of its 16 waves run the MFMAs.
-struct Wg2 {
-    static constexpr int CIN = 2, NJ = 9 * CIN, NTL = (NJ + 15) / 16, W = 31, DW = 32, AH = 33, AW = 40;
-    static constexpr size_t bytes() { return ((size_t)32 * W * DW + (size_t)CIN * AH * AW) * 2; }
-};
-
-__global__ __launch_bounds__(WT) void cnn_wgrad2_kernel(WgradArgs a) {
-    using WS = Wg2;
-    constexpr int CIN = WS::CIN, NJ = WS::NJ, NTL = WS::NTL, W = WS::W, DW = WS::DW, AW = WS::AW,
-                  AH = WS::AH;
-    extern __shared__ __align__(16) bf16 sm[];
-    bf16 *dzl = sm;                             // [32][31][32]   channel-first dZ
-    bf16 *al = sm + 32 * W * DW;                // [CIN][33][40]  channel-first input, x' = x + 1
-    const int b = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col = lane & 15, g = lane >> 4;
-    constexpr int NWV = WT / 64, NMAX = (NTL + 1 + NWV - 1) / NWV;   // weight tiles and the bias tile
-    floatx4 acc[2][NMAX];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < NMAX; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int i = tid; i < 32 * W * DW / 8; i += WT) ((uint4 *)dzl)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (int i = tid; i < CIN * AH * AW / 8; i += WT) ((uint4 *)al)[i] = make_uint4(0u, 0u, 0u, 0u);
-    __syncthreads();
-    const int nv = *a.nvalid;
-    for (int k = b; k < nv; k += gridDim.x) {
-        const int n = a.order[k];
-        const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
-        const bf16 *as = a.ain + (size_t)n * a.npx * CIN;
-        // dZ: a thread takes a pair of horizontally adjacent pixels (every
-        // channel: 16-byte loads) and writes each channel's pair as one
-        // 4-byte word of the channel-first tile; for one channel the lanes of
-        // a wave write consecutive words (no bank conflicts).  x = 31 reads
-        // as zero.
-        constexpr int NPAIR = W * 16;                    // 31 rows x 16 pairs
-        for (int q0 = tid; q0 < NPAIR; q0 += WT) {
-            const int y = q0 / 16, m = q0 % 16;
-            uint4 v0[4], v1[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                v0[q] = ((const uint4 *)(dzs + (size_t)(y * W + 2 * m) * 32))[q];
-                v1[q] = 2 * m + 1 < W ? ((const uint4 *)(dzs + (size_t)(y * W + 2 * m + 1) * 32))[q]
-                                      : make_uint4(0u, 0u, 0u, 0u);
-            }
-#pragma unroll
-            for (int o = 0; o < 32; ++o) {
-                const uint32_t wa = (&v0[o >> 3].x)[(o >> 1) & 3], wb = (&v1[o >> 3].x)[(o >> 1) & 3];
-                *(uint32_t *)&dzl[(o * W + y) * DW + 2 * m] =
-                    (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
-            }
-        }
-        for (int p = tid; p < a.npx; p += WT) {   // both channels of a pixel: one 4-byte load
-            const uint32_t w = ((const uint32_t *)as)[p];
-            al[(0 * AH + p / W + 1) * AW + p % W + 1] = __builtin_bit_cast(bf16, (uint16_t)(w & 0xffffu));
-            al[(1 * AH + p / W + 1) * AW + p % W + 1] = __builtin_bit_cast(bf16, (uint16_t)(w >> 16));
-        }
-        __syncthreads();
-        for (int y = 0; y < W; ++y) {
-            bf16x8 A0 = *(const bf16x8 *)&dzl[(col * W + y) * DW + 8 * g];
-            bf16x8 A1 = *(const bf16x8 *)&dzl[((16 + col) * W + y) * DW + 8 * g];
-#pragma unroll
-            for (int jj = 0; jj < NMAX; ++jj) {
-                const int nt = wave + NWV * jj;
-                if (nt > NTL) break;
-                const int j = nt * 16 + col;
-                bf16x8 B;
-                if (nt == NTL) {
-                    // the bias tile: every column of B is one, so each column
-                    // of the product is db[o] = sum_p dZ[p][o]
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) B[e] = (bf16)1.f;
-                } else if (j < NJ) {
-                    const int tap = j / CIN, c = j % CIN, dy = tap / 3 - 1, dx = tap % 3 - 1;
-                    const bf16 *rp = &al[(c * AH + y + 1 + dy) * AW + 1 + dx + 8 * g];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) B[e] = rp[e];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) B[e] = (bf16)0.f;
-                }
-                acc[0][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B, acc[0][jj], 0, 0, 0);
-                acc[1][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B, acc[1][jj], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
-    float *part = a.part + (size_t)b * (32 * NJ + 32);
-#pragma unroll
-    for (int jj = 0; jj < NMAX; ++jj) {
-        const int nt = wave + NWV * jj;
-        if (nt > NTL) break;
-        if (nt == NTL) {
-            if (col == 0) {
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) part[32 * NJ + mt * 16 + 4 * g + r] = acc[mt][jj][r];
-            }
-            continue;
-        }
-        const int j = nt * 16 + col;
-        if (j >= NJ) continue;
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) part[(mt * 16 + 4 * g + r) * NJ + j] = acc[mt][jj][r];
-    }
-}
-
 // Weight gradients of a 32-channel layer, streamed in bands of R = 16 image
 // rows so that a workgroup needs 78 KB of LDS and two fit a CU: while one
 // stages a band from HBM the other runs its MFMAs.  Eight waves per
@@ -542,6 +429,142 @@ __global__ __launch_bounds__(WT32, 4) void cnn_wgrad32_kernel(WgradArgs a) {
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[32 * NJ + mt * 16 + 4 * g + r] = acc[mt][0][r];
+    }
+}
+
+// Weight gradients of the first layer (2 input channels: 18 weight columns
+// plus the bias), streamed in the same bands of 16 rows as the 32-channel
+// kernel (36 KB of LDS, four workgroups per CU).  Wave 0 takes weight columns
+// 0..15 (taps 0..7), wave 1 columns 16..17 (tap 8; the rest of its tile is
+// zero), wave 2 the bias tile; every wave stages.  A column's tap and channel
+// vary across the lanes, so each lane shifts its two 16-byte reads by its own
+// dx.
+struct Wg2 {
+    static constexpr int R = 16, W = 31, CIN = 2, NJ = 9 * CIN;
+    static constexpr int DZS = R * 32 + 8;      // dZ [32 o][R rows][32 x], as Wg32
+    static constexpr int AR = R + 2, AW = 40;   // input rows y0 - 1 .. y0 + R, column x + 1
+    static constexpr int AS = AR * AW + 8;
+    static constexpr int NDZ = R * 16, NITEM = NDZ + AR * 16;   // pixel pairs per band
+    static constexpr size_t bytes() { return ((size_t)32 * DZS + (size_t)CIN * AS) * 2; }
+};
+
+__global__ __launch_bounds__(WT32, 4) void cnn_wgrad2_kernel(WgradArgs a) {
+    using S = Wg2;
+    constexpr int R = S::R, W = S::W, NJ = S::NJ, DZS = S::DZS, AW = S::AW, AS = S::AS;
+    extern __shared__ __align__(16) bf16 sm[];
+    bf16 *dzl = sm;
+    bf16 *al = sm + 32 * DZS;
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, g = lane >> 4;
+    floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+    for (int i = tid; i < (int)(S::bytes() / 16); i += WT32) ((uint4 *)sm)[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    // this lane's weight column (waves 0 and 1): tap, channel, offsets
+    const int j = wave * 16 + col;
+    const bool jin = wave < 2 && j < NJ;
+    const int tap = jin ? j / 2 : 0, cc = j % 2, dy = tap / 3 - 1, dx1 = tap % 3;   // dx1 = dx + 1
+    // items as in the 32-channel kernel: q < NDZ a dZ pixel pair (all 32
+    // channels), the rest an input pixel pair (x = 2m-1, 2m; one 4-byte word
+    // of both channels each)
+    auto load = [&](const bf16 *dzs, const bf16 *as, int y0, int q, uint4 (&v)[2][4]) {
+        const bool isdz = q < S::NDZ;
+        const int qq = isdz ? q : q - S::NDZ, m = qq % 16;
+        const int y = isdz ? y0 + qq / 16 : y0 - 1 + qq / 16;
+        const int x0 = isdz ? 2 * m : 2 * m - 1;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int x = x0 + p;
+            const bool in = y >= 0 && y < W && x >= 0 && x < W;
+            if (isdz) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    v[p][k] = in ? ((const uint4 *)(dzs + (size_t)(y * W + x) * 32))[k] : make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                v[p][0].x = in ? ((const uint32_t *)as)[y * W + x] : 0u;
+            }
+        }
+    };
+    auto store = [&](int q, const uint4 (&v)[2][4]) {
+        const bool isdz = q < S::NDZ;
+        const int qq = isdz ? q : q - S::NDZ, m = qq % 16, r = qq / 16;
+        if (isdz) {
+            uint32_t *dst = (uint32_t *)&dzl[r * 32 + 2 * m];
+#pragma unroll
+            for (int o = 0; o < 32; ++o) {
+                const uint32_t wa = (&v[0][o >> 3].x)[(o >> 1) & 3], wb = (&v[1][o >> 3].x)[(o >> 1) & 3];
+                dst[o * (DZS / 2)] = (o & 1) ? ((wa >> 16) | (wb & 0xffff0000u)) : ((wa & 0xffffu) | (wb << 16));
+            }
+        } else {
+            uint32_t *dst = (uint32_t *)&al[r * AW + 2 * m];
+            const uint32_t wa = v[0][0].x, wb = v[1][0].x;
+            dst[0] = (wa & 0xffffu) | (wb << 16);                       // channel 0
+            dst[AS / 2] = (wa >> 16) | (wb & 0xffff0000u);              // channel 1
+        }
+    };
+    const int q1 = tid + WT32;
+    const bool two = q1 < S::NITEM;
+    const int nv = *a.nvalid;
+    for (int k = b; k < nv; k += gridDim.x) {
+        const int n = a.order[k];
+        const bf16 *dzs = a.dz + (size_t)n * a.npx * 32;
+        const bf16 *as = a.ain + (size_t)n * a.npx * 2;
+        for (int y0 = 0; y0 < W; y0 += R) {
+            {
+                uint4 v0[2][4];
+                load(dzs, as, y0, tid, v0);
+                store(tid, v0);
+            }
+            if (two) {
+                uint4 v1[2][4];
+                load(dzs, as, y0, q1, v1);
+                store(q1, v1);
+            }
+            __syncthreads();
+            const int nr = min(R, W - y0);
+            if (wave < 3) {
+                for (int i = 0; i < nr; ++i) {
+                    const bf16x8 A0 = *(const bf16x8 *)&dzl[col * DZS + i * 32 + 8 * g];
+                    const bf16x8 A1 = *(const bf16x8 *)&dzl[(16 + col) * DZS + i * 32 + 8 * g];
+                    bf16x8 B;
+                    if (wave == 2) {
+                        // the bias tile: every column of B is one
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) B[e] = (bf16)1.f;
+                    } else {
+                        uint4 sel = make_uint4(0u, 0u, 0u, 0u);
+                        if (jin) {
+                            const bf16 *rp = &al[cc * AS + (i + 1 + dy) * AW + 8 * g];
+                            const uint4 lo = *(const uint4 *)rp, hi = *(const uint4 *)(rp + 8);
+                            uint4 s1;
+                            s1.x = __builtin_amdgcn_alignbyte(lo.y, lo.x, 2);
+                            s1.y = __builtin_amdgcn_alignbyte(lo.z, lo.y, 2);
+                            s1.z = __builtin_amdgcn_alignbyte(lo.w, lo.z, 2);
+                            s1.w = __builtin_amdgcn_alignbyte(hi.x, lo.w, 2);
+                            const uint4 s2 = make_uint4(lo.y, lo.z, lo.w, hi.x);
+                            sel = dx1 == 0 ? lo : (dx1 == 1 ? s1 : s2);
+                        }
+                        B = *(const bf16x8 *)&sel;
+                    }
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B, acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B, acc[1], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // partials: dW[o][tap][c] at o * NJ + tap * 2 + c (= o * NJ + j); db after
+    float *part = a.part + (size_t)b * (32 * NJ + 32);
+    if (jin) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[(mt * 16 + 4 * g + r) * NJ + j] = acc[mt][r];
+    } else if (wave == 2 && col == 0) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[32 * NJ + mt * 16 + 4 * g + r] = acc[mt][r];
     }
 }
 
@@ -1144,7 +1167,7 @@ int wgrad2_launch(argus_ctx *ctx, const WgradArgs &wa, int T) {
     size_t lds = Wg2::bytes();
     ARGUS_HIP_CHECK(ctx, hipFuncSetAttribute((const void *)cnn_wgrad2_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(cnn_wgrad2_kernel, dim3(T * WG_GROUPS), dim3(WT), lds, ctx->stream, wa);
+    hipLaunchKernelGGL(cnn_wgrad2_kernel, dim3(T * WG_GROUPS), dim3(WT32), lds, ctx->stream, wa);
     ARGUS_HIP_CHECK(ctx, hipGetLastError());
     return ARGUS_OK;
 }
