@@ -184,7 +184,7 @@ def cpu_baseline(fp, spec_o, n_tiles, tiles=16):
     science frame, coadd and normal equations; one FP64 solve of their sum;
     per tile subtraction and detection.  Mpix/s = sampled tile pixels / wall
     time.  Also the whole path on the 1024^2 CPU-sized pair in one process
-    on one core.  At most 16 workers (a one-GPU machine's share of its host)."""
+    on one core.  At most 16 workers (the host cores that go with one GPU)."""
     import multiprocessing as mp
     import oracle
     from paper_2207_14304_amd import synth
