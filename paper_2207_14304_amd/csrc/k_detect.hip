@@ -5,10 +5,12 @@
 //   and one halo row/column on each side in LDS (4-pixel vector loads), writes
 //   snr and det_mask (4-pixel vector stores) and counts the candidates of
 //   each 256-pixel row segment.
-// scan_tiles / scan_top: exclusive scan of the segment counts (1024-count
-//   tiles in parallel, then the tile totals) -> raster-order offsets.
-// detect_emit: one wave per segment with candidates writes them in raster
-//   order at their offsets and measures the PSF flux in FP64.
+// scan_tiles: exclusive scan of the segment counts within 1024-count tiles,
+//   and each tile's total.
+// detect_emit: a wave takes 64 segments (one scan tile's), adds the totals of
+//   the tiles before theirs, and for each segment with candidates writes them
+//   in raster order at their offsets and measures the PSF flux in FP64; the
+//   first wave writes the candidate count.
 //
 // Source mode (argus_detect_sources): the same kernels on a calibrated frame,
 // with D = cal - background evaluated from the filtered cell grid per pixel,
@@ -24,6 +26,7 @@ namespace {
 constexpr int SEG = 256, ROWS = 16, NTHR = 256;   // a wave covers a 256-pixel row, 4 px a lane
 constexpr int LW = SEG + 8;                        // LDS row: [3] = x0-1, [4..259], [260] = x0+256
 constexpr int STILE = 1024;                        // counts per scan tile
+static_assert(STILE % 64 == 0, "a wave's 64 segments lie in one scan tile");
 
 struct DetArgs {
     const float *diff, *dvar;
@@ -33,7 +36,6 @@ struct DetArgs {
     int32_t *counts;           // [nseg]   candidates per row segment
     int32_t *local;            // [nseg]   offset within its scan tile
     int32_t *tile_sum;         // [ntile]
-    int32_t *tile_off;         // [ntile]
     const float *psf;
     argus_candidate *cands;
     argus_source *srcs;
@@ -221,23 +223,6 @@ __global__ __launch_bounds__(NTHR) void scan_tiles_kernel(DetArgs a) {
     if (tid == NTHR - 1) a.tile_sum[t] = wbase + inc;
 }
 
-__global__ __launch_bounds__(64) void scan_top_kernel(DetArgs a) {
-    const int lane = threadIdx.x;
-    int carry = 0;
-    for (int b = 0; b < a.ntile; b += 64) {
-        const int j = b + lane;
-        const int v = j < a.ntile ? a.tile_sum[j] : 0;
-        int inc = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            int n = __shfl_up(inc, off);
-            if (lane >= off) inc += n;
-        }
-        if (j < a.ntile) a.tile_off[j] = carry + inc - v;
-        carry += __shfl(inc, 63);
-    }
-    if (lane == 0) *a.n_cands = carry;
-}
-
 template <bool SRC>
 __global__ __launch_bounds__(NTHR) void detect_emit_kernel(DetArgs a) {
     const int lane = threadIdx.x & 63;
@@ -245,13 +230,26 @@ __global__ __launch_bounds__(NTHR) void detect_emit_kernel(DetArgs a) {
     // segments hold no candidate) and visits those with candidates; groups of
     // 64 segments are strided over all waves
     const int nw = gridDim.x * (NTHR / 64);
+    // the total goes out from the first wave (the sum of every scan tile)
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        int tot = 0;
+        for (int t = lane; t < a.ntile; t += 64) tot += a.tile_sum[t];
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+        if (lane == 0) *a.n_cands = tot;
+    }
     for (int s0 = (blockIdx.x * (NTHR / 64) + (threadIdx.x >> 6)) * 64; s0 < a.nseg; s0 += nw * 64) {
         const bool has = s0 + lane < a.nseg && a.counts[s0 + lane] != 0;
         uint64_t segs = __ballot(has);
+        if (!segs) continue;
+        // the 64 segments share one scan tile (STILE is a multiple of 64):
+        // its offset is the sum of the tiles before it
+        int toff = 0;
+        for (int t = lane; t < s0 / STILE; t += 64) toff += a.tile_sum[t];
+        for (int off = 32; off > 0; off >>= 1) toff += __shfl_xor(toff, off);
         while (segs) {
             const int seg = s0 + __builtin_ctzll(segs);
             segs &= segs - 1;
-            int idx = a.tile_off[seg / STILE] + a.local[seg];
+            int idx = toff + a.local[seg];
             const int y = seg / a.nsx, x0 = (seg % a.nsx) * SEG;
             const int64_t orow = (int64_t)y * a.pitch;
             const int K = 2 * a.r + 1;
@@ -352,14 +350,13 @@ int launch_detect_any(argus_ctx *ctx, argus_dims d, const float *diff, const flo
     auto al = [](const void *p, uintptr_t m) { return p == nullptr || ((uintptr_t)p % m) == 0; };
     a.vec = (d.pitch % 4 == 0) && al(diff, 16) && al(dvar, 16) && al(snr, 16) && al(dmask, 4) &&
             al(det, 4);
-    size_t need = ((size_t)2 * a.nseg + 2 * a.ntile + 64) * sizeof(int32_t);
+    size_t need = ((size_t)2 * a.nseg + a.ntile + 64) * sizeof(int32_t);
     int rc = argus_ws_reserve(ctx, need);
     if (rc) return rc;
     int32_t *w = (int32_t *)ctx->ws;
     a.counts = w;
     a.local = w + a.nseg;
     a.tile_sum = w + 2 * (size_t)a.nseg;
-    a.tile_off = a.tile_sum + a.ntile;
     argus_time_begin(ctx);
     const dim3 mg(a.nsx * ((d.height + ROWS - 1) / ROWS));
     if (src)
@@ -370,7 +367,6 @@ int launch_detect_any(argus_ctx *ctx, argus_dims d, const float *diff, const flo
     argus_time_end(ctx, src ? "source_map" : "detect_map");
     argus_time_begin(ctx);
     hipLaunchKernelGGL(scan_tiles_kernel, dim3(a.ntile), dim3(NTHR), 0, ctx->stream, a);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(64), 0, ctx->stream, a);
     // one wave per 64 segments, at most enough to fill the device a few times over
     const int eblocks = std::max(1, std::min((a.nseg + 255) / 256, 8 * std::max(ctx->n_cu, 1)));
     if (src)
