@@ -52,7 +52,7 @@ struct argus_batch {
 
 namespace {
 
-constexpr int BW = 128, PXT = 8, DROWS = 4;
+constexpr int BW = 128, PXT = 4, DROWS = 4;
 
 struct BatchArgs {
     const argus_frame *frames;
